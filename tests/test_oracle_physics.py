@@ -1,0 +1,168 @@
+"""Statistical physics pins of the CPU oracle (runs of a few seconds each).
+
+  - equilibrium temperature: the time-centred kT estimate equals the set kT
+    (fluctuation-dissipation, Sec. 2.1) within 1 %;
+  - Groot-Warren equation of state p = rho kT + 0.101 a rho^2 (the empirical
+    high-density fit of Groot & Warren, J. Chem. Phys. 107, 4423 (1997)),
+    and its exact mean-field limit alpha -> pi/30 for a -> 0;
+  - energy conservation of the kick-drift integrator with the conservative
+    force alone, checked against a potential computed here independently;
+  - periodic Poiseuille flow (Sec. 4.2, Eq. 11): antisymmetric two-half
+    parabola, with the viscosity of the Groot-Warren fluid of Table 1
+    (a = 25, gamma = 6.75, rho = 3, kT = 1, dt = 0.04: eta = 0.91).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_04712_amd import inputs
+
+pytestmark = pytest.mark.slow
+
+
+def _block_se(x, nblocks=10):
+    b = np.array_split(np.asarray(x), nblocks)
+    m = np.array([bb.mean() for bb in b])
+    return m.std(ddof=1) / math.sqrt(nblocks)
+
+
+@pytest.fixture(scope="module")
+def equilibrium_run():
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, kT=1.0, seed=11)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    diag, _, _, _ = oracle.step(x, v, ids, cells, p, seed=11, step0=0, nsteps=6000)
+    return {k: val[1000:] for k, val in diag.items()}
+
+
+def test_equilibrium_kT(equilibrium_run):
+    kt = equilibrium_run["kT_centred"]
+    m, se = kt.mean(), _block_se(kt)
+    assert abs(m - 1.0) < 0.01, (m, se)
+    assert abs(m - 1.0) < 3 * se + 2e-3, (m, se)
+
+
+def test_half_step_estimator_is_biased_up(equilibrium_run):
+    # the half-step KE carries the friction bias the time-centred one avoids
+    n = 1536
+    kt_half = 2.0 * equilibrium_run["ke_half"] / (3.0 * (n - 1))
+    assert kt_half.mean() > equilibrium_run["kT_centred"].mean()
+
+
+def _eos_alpha(cells, rho, a, seed, nsteps=3000, discard=500):
+    pos, vel = inputs.uniform_state(cells, density=rho, kT=1.0, seed=seed)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    p = oracle.make_params(a=a, gamma=4.5, kT=1.0, dt=0.01)
+    diag, _, _, _ = oracle.step(x, v, ids, cells, p, seed, 0, nsteps)
+    kt = diag["kT_centred"][discard:].mean()
+    pr = diag["pressure"][discard:].mean()
+    return (pr - rho * kt) / (a * rho * rho)
+
+
+def test_groot_warren_pressure_high_density():
+    """The fit p = rho kT + 0.101 a rho^2 is Groot and Warren's high-density
+    form; at rho = 8, a = 25 the excess coefficient must be 0.101 within 3 %."""
+    alpha = _eos_alpha((5, 5, 5), 8.0, 25.0, seed=21)
+    assert abs(alpha - 0.101) < 0.03 * 0.101, alpha
+
+
+def test_pressure_mean_field_limit():
+    """For a -> 0 the pair distribution tends to 1 and the virial gives
+    alpha = (2 pi / 3) int_0^1 r^3 (1 - r) dr = pi / 30 exactly."""
+    alpha = _eos_alpha((6, 6, 6), 3.0, 0.25, seed=22)
+    assert abs(alpha - math.pi / 30.0) < 0.04 * math.pi / 30.0, alpha
+
+
+def test_pressure_rho3_below_fit(equilibrium_run):
+    """At rho = 3 the structured fluid sits below the high-density fit and
+    above zero excess; the mean-field value is an upper bound."""
+    rho, a = 3.0, 25.0
+    kt = equilibrium_run["kT_centred"].mean()
+    alpha = (equilibrium_run["pressure"].mean() - rho * kt) / (a * rho * rho)
+    assert 0.08 < alpha < 0.101, alpha
+
+
+def _potential(x, L, a):
+    # U = sum_{i<j} (a/2)(1 - r)^2 for r < 1: the potential whose negative
+    # gradient is the conservative force of Eq. 3 (written here independently)
+    n = len(x)
+    U = 0.0
+    for i in range(n - 1):
+        d = x[i] - x[i + 1:]
+        d -= L * np.rint(d / L)
+        r = np.sqrt((d * d).sum(axis=1))
+        r = r[r < 1.0]
+        U += 0.5 * a * np.sum((1.0 - r) ** 2)
+    return U
+
+
+def test_conservative_energy_has_no_drift():
+    cells = (6, 6, 6)
+    L = np.array(cells, dtype=np.float64)
+    pos, vel = inputs.uniform_state(cells, density=3.0, kT=1.0, seed=12)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    a, dt = 25.0, 0.01
+    p = oracle.make_params(a=a, gamma=0.0, kT=0.0, dt=dt)
+    # settle the random start first
+    oracle.step(x, v, ids, cells, p, 0, 0, 300, want_diag=False)
+    E = []
+    for k in range(40):
+        U = _potential(x, L, a)
+        diag, _, _, _ = oracle.step(x, v, ids, cells, p, 0, 0, 1)
+        E.append(diag["ke_centred"][0] + U)
+        oracle.step(x, v, ids, cells, p, 0, 0, 49, want_diag=False)
+    E = np.array(E)
+    rel = (E - E.mean()) / abs(E.mean())
+    assert np.max(np.abs(rel)) < 2e-3, rel
+    slope = np.polyfit(np.arange(len(E)), E, 1)[0] * len(E) / abs(E.mean())
+    assert abs(slope) < 1e-3, slope
+
+
+def test_periodic_poiseuille_profile():
+    """Reverse-Poiseuille flow along x, gradient along y, L_y = 8.  For a
+    Newtonian fluid v_x(y) = -rho f y (L/2 - y) / (2 eta) on [0, L/2] and the
+    mirror image with opposite sign above (Eq. 11; the printed profile has the
+    opposite sign of its force, and the force is followed here)."""
+    cells = (8, 8, 8)
+    rho, a, gamma, kT, dt, f = 3.0, 25.0, 6.75, 1.0, 0.04, 0.1
+    nb = 16
+    pos, vel = inputs.uniform_state(cells, density=rho, kT=kT, seed=13)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    p = oracle.make_params(a=a, gamma=gamma, kT=kT, dt=dt, body_f=f, flow_axis=0, grad_axis=1)
+    oracle.step(x, v, ids, cells, p, 13, 0, 1500, want_diag=False)
+    sums, cnts = [], []
+    for k in range(10):
+        _, ps, pc, _ = oracle.step(x, v, ids, cells, p, 13, 1500 + 300 * k, 300, nbins=nb,
+                                   want_diag=False)
+        sums.append(ps)
+        cnts.append(pc)
+    prof = np.array([s / c for s, c in zip(sums, cnts)])       # 10 blocks x nb bins
+    mean = prof.mean(axis=0)
+    err = prof.std(axis=0, ddof=1) / math.sqrt(len(prof))
+    L = 8.0
+    y = (np.arange(nb) + 0.5) * L / nb
+    # sign follows the force: negative in the lower half, positive above
+    assert np.all(mean[: nb // 2] < 0) and np.all(mean[nb // 2:] > 0)
+    # antisymmetry v(y) = -v(y + L/2)
+    assert np.all(np.abs(mean[: nb // 2] + mean[nb // 2:]) < 4 * np.hypot(err[: nb // 2], err[nb // 2:]))
+    # bin-averaged shape g(y) such that v = (rho f / (2 eta)) * g
+    def shape(y0, y1):
+        # average of s(y) (L/2 - s(y)) with s = y mod L/2, signed, over a bin
+        yy = np.linspace(y0, y1, 201)
+        s = np.mod(yy, L / 2)
+        sign = np.where(yy <= L / 2, -1.0, 1.0)
+        return np.mean(sign * s * (L / 2 - s))
+    g = np.array([shape(i * L / nb, (i + 1) * L / nb) for i in range(nb)])
+    w = 1.0 / err ** 2
+    c = np.sum(w * g * mean) / np.sum(w * g * g)             # c = rho f / (2 eta)
+    chi2 = np.sum(w * (mean - c * g) ** 2) / (nb - 1)
+    eta = rho * f / (2.0 * c)
+    assert chi2 < 4.0, chi2
+    assert abs(eta - 0.91) < 0.15 * 0.91, eta
