@@ -1,0 +1,218 @@
+/*
+ * dpd.h -- C-ABI of the MI355X (gfx950) DPD solvent library.
+ *
+ * The library advances a periodic box of dissipative-particle-dynamics
+ * solvent particles on one GPU.  One time step is the hot path of the
+ * Mirheo paper (arXiv 1911.04712):
+ *
+ *   1. cell binning: particles are sorted into unit cells (edge r_c = 1) by a
+ *      stable counting sort (Sec. 3.2; time-stepping step 1 of Sec. 3.1);
+ *   2. pair forces: F_i = sum_j (F^C_ij + F^D_ij + F^R_ij) over r_ij < r_c
+ *      (Sec. 2.1, Eqs. 2-5, with w_R = w = 1 - r, w_D = w^2,
+ *      sigma^2 = 2 gamma kT), the random term being sigma w xi_ij / sqrt(dt);
+ *      plus the optional periodic-Poiseuille body force (Sec. 4.2, Eq. 11);
+ *   3. fused velocity-Verlet (Sec. 3.1, time-stepping step 5):
+ *      v^{n+1/2} = v^{n-1/2} + dt f^n / m,  x^{n+1} = x^n + dt v^{n+1/2},
+ *      followed by the periodic wrap; FP64 reductions of momentum, kinetic
+ *      energy and the flow profile are fused into this step.
+ *
+ * xi_ij is Box-Muller applied to the first two words of Philox4x32-10
+ * (Salmon et al., SC'11) with counter (min id, max id, step mod 2^32, 0)
+ * and key (seed mod 2^32, seed >> 32); u1 = ((w0 >> 8) + 1) 2^-24,
+ * u2 = (w1 >> 8) 2^-24, xi = sqrt(-2 ln u1) cos(2 pi u2).  `step` counts
+ * force evaluations since dpd_set_state.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status (DPD_OK or a negative DPD_E* code)
+ *     and never throws.  dpd_last_error() gives a thread-local message for
+ *     the last failing call of the calling thread.
+ *   - Device memory is the caller's: the box lives inside a workspace the
+ *     caller allocates (size from dpd_workspace_bytes) and frees after
+ *     dpd_destroy.  The library never frees caller memory.  It allocates no
+ *     device memory for particle state.
+ *   - Pointers flagged `where` are host pointers for DPD_HOST and device
+ *     pointers for DPD_DEVICE.
+ *   - Work is enqueued on the HIP stream given at creation.  dpd_step is
+ *     asynchronous; reads and stats synchronise that stream.
+ *   - Particle arrays exchanged with the caller are row i = particle id i,
+ *     three floats per row (x, y, z).  Internally particles are kept in cell
+ *     order; dpd_read_raw exposes that order.
+ *   - Units: r_c = 1, so a box of cells (L_x, L_y, L_z) has edges L_x, L_y,
+ *     L_z; every edge is an integer >= 3.
+ *   - Positions live on a fixed grid: every stored coordinate is a multiple
+ *     of q = spacing of FP32 numbers at max(L_x, L_y, L_z)
+ *     (2^(floor(log2 L_max) - 23)).  Positions passed to dpd_set_state are
+ *     rounded to that grid; dpd_position_grid returns q.
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+    DPD_OK = 0,
+    DPD_EINVAL = -1,     /* invalid argument (null pointer, size, range)        */
+    DPD_ENOMEM = -2,     /* workspace or pool too small; host allocation failed */
+    DPD_EDEVICE = -3,    /* a HIP call failed; message in dpd_last_error()     */
+    DPD_ESTATE = -4,     /* call out of order (e.g. step before set_state)     */
+    DPD_ENONFINITE = -5, /* a non-finite force, velocity or position was seen  */
+    DPD_EAGAIN = -6,     /* result not ready yet                                */
+    DPD_EBUSY = -7,      /* no free slot or memory right now                    */
+    DPD_ENOTFOUND = -8   /* unknown ticket                                      */
+};
+
+enum { DPD_HOST = 0, DPD_DEVICE = 1 };
+
+/* quantities for dpd_read */
+enum {
+    DPD_POS = 0,          /* x^n (after the last step), wrapped into [0, L)           */
+    DPD_VEL = 1,          /* stored half-step velocity v^{n-1/2}                      */
+    DPD_VEL_CENTRED = 2,  /* v^{n-1/2} - dt f^{n-1} / (2m): time level of the last force */
+    DPD_FORCE = 3         /* f^{n-1}: total force of the last step (pairs + body)     */
+};
+
+/* flags of dpd_params.flags */
+enum {
+    DPD_FLAG_VIRIAL = 1   /* also accumulate the conservative virial each step   */
+};
+
+typedef struct dpd_box_s* dpd_box;
+
+/* Box geometry: edges in unit cells (each >= 3) and particle count. */
+typedef struct {
+    int32_t cells[3];
+    int32_t reserved;     /* must be 0 */
+    int64_t n;            /* 0 <= n <= 2^30 */
+} dpd_geom;
+
+/* Model parameters (Sec. 2.1, Eqs. 3-5; Sec. 4.2, Eq. 11).
+ * sigma = sqrt(2 gamma kT) is derived.  Required: dt > 0, mass > 0,
+ * gamma >= 0, kT >= 0, all finite; flow_axis != grad_axis in {0,1,2};
+ * profile_bins in [0, 4096]. */
+typedef struct {
+    double a;             /* conservative amplitude                                */
+    double gamma;         /* dissipative coefficient                               */
+    double kT;            /* temperature                                           */
+    double dt;            /* time step                                             */
+    double mass;          /* particle mass                                         */
+    double body_f;        /* periodic-Poiseuille amplitude f (0 = no body force):
+                             -f along flow_axis where the grad_axis coordinate is
+                             <= L/2, +f above                                      */
+    int32_t flow_axis;
+    int32_t grad_axis;
+    int32_t profile_bins; /* slabs along grad_axis for the flow profile (0 = off)  */
+    int32_t flags;        /* DPD_FLAG_*                                            */
+} dpd_params;
+
+/* Diagnostics, all reduced in FP64 on the GPU in a fixed order.
+ * "last" values describe the most recent step n -> n+1. */
+typedef struct {
+    double momentum[3];       /* last: sum m v^{n+1/2}                                 */
+    double ke_half;           /* last: sum m |v^{n+1/2}|^2 / 2                        */
+    double ke_centred;        /* last: sum m |v^{n-1/2} + dt f^n/(2m)|^2 / 2           */
+    double kT_centred;        /* last: 2 ke_centred / (3 (N - 1))                     */
+    double virial;            /* last: sum_{i<j} r_ij . F^C_ij (DPD_FLAG_VIRIAL)      */
+    double pressure;          /* last: rho kT_centred + virial / (3 V)                */
+    double sum_kT_centred;    /* sums over the steps since the last reset ...         */
+    double sum_pressure;
+    double sum_momentum[3];
+    uint64_t nsamples;        /* ... and their number                                  */
+    uint64_t step;            /* force evaluations since dpd_set_state                 */
+    int32_t nonfinite;        /* 1 if a non-finite value was seen since set_state      */
+    int32_t escaped;          /* 1 if a particle moved >= 1 per axis in one step       */
+} dpd_stats;
+
+/* ---- single box -------------------------------------------------------- */
+
+/* Spacing q of the position grid of a geometry (see conventions). */
+int dpd_position_grid(const dpd_geom* geom, double* q);
+
+/* Bytes of device memory the box needs (also its admission footprint). */
+int dpd_workspace_bytes(const dpd_geom* geom, size_t* bytes);
+
+/* Create a box inside `dev_ws` (device memory of at least
+ * dpd_workspace_bytes, 256-byte aligned), working on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The workspace must outlive the
+ * box.  DPD_ENOMEM if ws_bytes is too small. */
+int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_stream, dpd_box* out);
+
+/* Set model parameters; validated as documented at dpd_params. */
+int dpd_set_params(dpd_box box, const dpd_params* params);
+
+/* Set the 64-bit seed of the random term. */
+int dpd_set_seed(dpd_box box, uint64_t seed);
+
+/* Load the state: pos and vel are n x 3 floats, row i = particle id i.
+ * pos must lie in [0, L) per axis (DPD_EINVAL otherwise; checked on the
+ * host for DPD_HOST, on the device for DPD_DEVICE), and is rounded to the
+ * position grid.  vel is taken as v^{-1/2}.  Resets the step counter and
+ * the accumulators.  Synchronises the stream. */
+int dpd_set_state(dpd_box box, const float* pos_n3, const float* vel_n3, int where);
+
+/* Bin the current state into cells without stepping (so dpd_read_raw
+ * reports the cell list of the current positions). */
+int dpd_build_cells(dpd_box box);
+
+/* Enqueue nsteps >= 0 full steps (bin, forces, integrate).  Requires
+ * params, seed and state.  Asynchronous. */
+int dpd_step(dpd_box box, int64_t nsteps);
+
+/* Copy one quantity (DPD_POS, DPD_VEL, DPD_VEL_CENTRED, DPD_FORCE) to
+ * out_n3 (n x 3 floats, row = id).  DPD_FORCE and DPD_VEL_CENTRED need at
+ * least one step.  Synchronises. */
+int dpd_read(dpd_box box, int what, float* out_n3, int where);
+
+/* The cell list of the last binning: pos4 / vel4 (n x 4 floats, may be
+ * NULL) in cell order, the 4th float of pos4 carrying the particle id as
+ * int32 bits; cell_start (n_cells + 1 int32, may be NULL).  Synchronises. */
+int dpd_read_raw(dpd_box box, float* pos4, float* vel4, int32_t* cell_start, int where);
+
+/* Diagnostics; DPD_ENONFINITE when the nonfinite flag is set (stats are
+ * still filled).  Synchronises. */
+int dpd_get_stats(dpd_box box, dpd_stats* out);
+
+/* Accumulated flow profile: sum of the time-centred flow-axis velocity and
+ * particle count per slab along grad_axis, over the steps since the last
+ * reset; nbins must equal params.profile_bins.  Synchronises. */
+int dpd_get_profile(dpd_box box, double* sum_v, double* count, int32_t nbins);
+
+/* Zero the accumulated sums (stats sums and the profile). */
+int dpd_reset_accumulators(dpd_box box);
+
+/* Destroy a box (NULL-safe).  Synchronises; the workspace may be freed after. */
+int dpd_destroy(dpd_box box);
+
+/* Run nsteps >= 1 steps eagerly (no graph) with a HIP event pair around
+ * each stage on the box stream, and return the mean device time per step of
+ * each stage in ms_out[4]: binning (chunk sums, scan, scatter, gather),
+ * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate.  The steps
+ * advance the box like dpd_step.  Synchronises. */
+int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
+
+/* Thread-local message of the last error (never NULL). */
+const char* dpd_last_error(void);
+
+/* ---- diagnostics of the random term (used by parity tests) -------------- */
+
+/* Philox4x32-10 words of n (counter, key) tuples on the GPU:
+ * ctr4 (n x 4 uint32), key2 (n x 2 uint32) -> out4 (n x 4 uint32).
+ * All pointers are `where`.  Synchronises. */
+int dpd_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, int where,
+               void* hip_stream);
+
+/* Box-Muller of n word pairs on the GPU, in the FP32 arithmetic of the
+ * force kernel: xi = sqrt(-2 ln u1) cos(2 pi u2).  Synchronises. */
+int dpd_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi, int where,
+                   void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPD_H */

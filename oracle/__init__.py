@@ -44,6 +44,7 @@ def lib():
         L.orc_philox_batch.argtypes = [ctypes.c_int64, u32p, u32p, u32p]
         L.orc_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         L.orc_box_muller.restype = ctypes.c_double
+        L.orc_box_muller_batch.argtypes = [ctypes.c_int64, u32p, u32p, dp]
         L.orc_pair_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u32p]
         L.orc_xi.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_xi.restype = ctypes.c_double
@@ -84,6 +85,14 @@ def pair_words(id_a, id_b, step, seed):
 
 def box_muller(w0, w1):
     return lib().orc_box_muller(int(w0), int(w1))
+
+
+def box_muller_batch(w0, w1):
+    a = np.ascontiguousarray(w0, dtype=np.uint32)
+    b = np.ascontiguousarray(w1, dtype=np.uint32)
+    out = np.empty(a.shape, dtype=np.float64)
+    lib().orc_box_muller_batch(a.size, _p(a, ctypes.c_uint32), _p(b, ctypes.c_uint32), _p(out, ctypes.c_double))
+    return out
 
 
 def xi(id_a, id_b, step, seed):

@@ -107,6 +107,13 @@ double orc_box_muller(uint32_t w0, uint32_t w1)
     return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
 }
 
+void orc_box_muller_batch(int64_t n, const uint32_t* w0, const uint32_t* w1, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = orc_box_muller(w0[i], w1[i]);
+}
+
 /* Philox words for the unordered pair {id_a, id_b} at force evaluation
  * `step` of a run with `seed`: counter (min id, max id, step mod 2^32, 0),
  * key (seed mod 2^32, seed >> 32).  Symmetric in (id_a, id_b) by

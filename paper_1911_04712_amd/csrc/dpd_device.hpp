@@ -1,0 +1,102 @@
+// dpd_device.hpp -- device-side building blocks of the DPD step on gfx950.
+//
+// Pair arithmetic is FP32 with explicit fmaf and the library is compiled
+// with -ffp-contract=off, so every kernel that evaluates a pair evaluates it
+// with the same instruction sequence.  Three design rules make the result
+// independent of which thread, tile or kernel evaluates a pair:
+//
+//  * positions live on the grid q = ulp_f32(L_max) (see include/dpd.h), so a
+//    periodic image x +- L and every neighbour displacement r_i - r_j are
+//    exact in FP32; hence r_ji == -r_ij bit for bit;
+//  * the pair force is an odd function of (r_ij, v_ij) in FP32: negating both
+//    negates every product feeding e_ij . v_ij exactly, so F_ji == -F_ij;
+//  * forces are accumulated in 64-bit fixed point (2^31 units per force
+//    unit) with a truncating, odd-symmetric conversion, so sums are exact
+//    integers whose value does not depend on summation order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpd {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round multipliers and
+// Weyl key increments.
+constexpr uint32_t kPhM0 = 0xD2511F53u;
+constexpr uint32_t kPhM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhW0 = 0x9E3779B9u;
+constexpr uint32_t kPhW1 = 0xBB67AE85u;
+
+__host__ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhM0 * c.x;
+        const uint64_t p1 = (uint64_t)kPhM1 * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += kPhW0;
+        k1 += kPhW1;
+    }
+    return c;
+}
+
+// Gaussian xi from the first two Philox words (Box-Muller on 24-bit
+// uniforms u1 in (0, 1], u2 in [0, 1)).  v_log_f32 returns log2 and
+// v_cos_f32 takes its argument in revolutions, so cos(2 pi u2) needs no
+// argument scaling.
+__device__ __forceinline__ float box_muller(uint32_t w0, uint32_t w1)
+{
+    const float u1 = (float)((w0 >> 8) + 1u) * 0x1p-24f;
+    const float u2 = (float)(w1 >> 8) * 0x1p-24f;
+    const float minus_2ln2 = -1.3862943611198906f;
+    const float rad = __builtin_amdgcn_sqrtf(minus_2ln2 * __builtin_amdgcn_logf(u1));
+    return rad * __builtin_amdgcn_cosf(u2);
+}
+
+__device__ __forceinline__ float pair_xi(uint32_t id_i, uint32_t id_j, uint32_t step, uint32_t k0,
+                                         uint32_t k1)
+{
+    const uint32_t lo = min(id_i, id_j), hi = max(id_i, id_j);
+    const uint4 w = philox10(make_uint4(lo, hi, step, 0u), k0, k1);
+    return box_muller(w.x, w.y);
+}
+
+// ---- fixed point ---------------------------------------------------------
+constexpr float kFxScale = 0x1p31f;        // units per force unit
+constexpr double kFxInv = 0x1p-31;
+constexpr float kFxLimit = 0x1p30f;        // |F| beyond this is reported as non-finite
+
+// Truncating conversion: fx(-f) == -fx(f).  Requires |f| < 2^30.
+__device__ __forceinline__ long long fx_of(float f)
+{
+    const float hi = truncf(f);
+    const float lo = (f - hi) * kFxScale;          // exact, |lo| < 2^31
+    return ((long long)(int)hi << 31) + (long long)(int)lo;
+}
+
+struct PairConst {
+    float a;          // conservative amplitude
+    float gamma;      // dissipative coefficient
+    float sig_rdt;    // sigma / sqrt(dt)
+    uint32_t k0, k1;  // Philox key = seed
+};
+
+// Scalar pair force along e_ij for r2 in (0, 1): returns F_ij / e_ij
+// (the vector force is ret * d * rinv).  d = r_i - r_j, dv = v_i - v_j.
+__device__ __forceinline__ float pair_scalar(float r2, float dx, float dy, float dz, float dvx, float dvy,
+                                             float dvz, float& rinv, float xi, const PairConst& pc)
+{
+    rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float w = 1.0f - r;
+    const float ev = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx)) * rinv;   // e_ij . v_ij
+    const float inner = fmaf(pc.sig_rdt, xi, fmaf(-pc.gamma * w, ev, pc.a));
+    return w * inner;
+}
+
+__device__ __forceinline__ float dist2(float dx, float dy, float dz)
+{
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+}  // namespace dpd

@@ -1,0 +1,108 @@
+// dpd_internal.hpp -- data layout shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dpd_device.hpp"
+
+namespace dpd {
+
+constexpr int kBlock = 256;             // threads per block of the streaming kernels
+constexpr int kScanChunk = 2048;        // cells per block of the cell-count scan
+constexpr int kIntegrateMaxBlocks = 2048;
+constexpr int kProfileMaxBins = 4096;
+constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred
+
+// Fixed-point scale of the flow-profile and virial accumulators.
+constexpr double kProfScale = 16777216.0;      // 2^24 units per velocity unit
+constexpr double kVirScale = 16777216.0;       // 2^24 units per virial unit
+
+// Device-resident counters and reductions.  Written only by kernels after
+// creation; read back by dpd_get_stats.
+struct DevStats {
+    unsigned long long step;        // force evaluations since set_state
+    unsigned int ticket;            // last-block-done counter of the integrate kernel
+    int nonfinite;
+    int escaped;
+    int pad0;
+    double last[kPartials];         // reductions of the last step
+    double sum_kT_centred;
+    double sum_pressure;
+    double sum_momentum[3];
+    unsigned long long nsamples;
+    long long virial_fx;            // conservative virial of the current step (fixed point)
+    double last_virial;
+    double last_pressure;
+    double last_kT_centred;
+};
+
+// Per-step constants of the integrate kernel.
+struct StepConst {
+    float dt;          // time step
+    float dtm;         // dt / m
+    float half_dtm;    // dt / (2 m)
+    float q;           // position grid
+    float inv_q;
+    float L[3];
+    int cells[3];
+    int flow_axis, grad_axis, nbins;
+    float grad_scale;  // nbins / L_grad
+    double mass;
+    double inv_dof;    // 1 / (3 (N - 1))  (0 when N < 2)
+    double inv_vol;
+    double rho;
+};
+
+struct ForceConst {
+    PairConst pc;
+    float L[3];
+    int cells[3];
+    float body_f;
+    int flow_axis, grad_axis;
+    float half_grad;   // L_grad / 2
+};
+
+// Layout of a box inside its caller-provided workspace.  All offsets are
+// 256-byte aligned.
+struct Layout {
+    size_t pos_a, vel_a;      // float4[n]  state, previous cell order (or id order)
+    size_t pos_b, vel_b;      // float4[n]  state binned into cell order
+    size_t force;             // float4[n]  total force of the last step, cell order
+    size_t keyslot;           // int2[n]    (cell, arrival slot) of pos_a
+    size_t perm;              // int[n]     cell order -> index into pos_a (unstable)
+    size_t out;               // float[3n]  staging of reads and writes in id order
+    size_t count;             // int[nc]    particles per cell
+    size_t cell_start;        // int[nc+1]
+    size_t bsum;              // int[nchunks]
+    size_t partials;          // double[kIntegrateMaxBlocks * kPartials]
+    size_t profile;           // long long[kProfileMaxBins * 2] (sum, count)
+    size_t stats;             // DevStats
+    size_t flags;             // int[4] scratch flags
+    size_t total;
+};
+
+Layout make_layout(int64_t n, int64_t nc);
+
+// ---- kernel launchers (dpd_kernels.hip) -----------------------------------
+hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s);
+hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4* pos, float4* vel,
+                             float q, float inv_q, const float* L, int* bad, hipStream_t s);
+hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s);
+hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* vel_in, int n, int nc,
+                      int* count, int* bsum, int* cell_start, int* perm, float4* pos_out, float4* vel_out,
+                      hipStream_t s);
+hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n,
+                               const ForceConst& fc, const unsigned long long* step, float4* force,
+                               int* nonfinite, hipStream_t s);
+hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const ForceConst& fc,
+                         DevStats* st, hipStream_t s);
+hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const float4* force, int n, const StepConst& sc,
+                            float4* pos_a, float4* vel_a, int* count, int2* keyslot, double* partials,
+                            long long* profile, DevStats* st, hipStream_t s);
+hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,
+                          float* out3, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, hipStream_t s);
+hipError_t launch_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi, hipStream_t s);
+
+}  // namespace dpd

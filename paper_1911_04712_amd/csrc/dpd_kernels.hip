@@ -1,0 +1,580 @@
+// dpd_kernels.hip -- gfx950 kernels of the DPD step: cell binning, pair
+// forces, fused velocity-Verlet with FP64 reductions, and read-back helpers.
+//
+// Binning (Sec. 3.2 of the Mirheo paper: cells of edge r_c, particles sorted
+// by cell) is a counting sort made stable and deterministic:
+//   keys    -- cell of each particle and an arrival slot from an atomic
+//              per-cell counter (fused into the integrate kernel, or k_keys
+//              after a state load);
+//   chunk   -- sums of 2048-cell chunks;
+//   scan    -- each block scans its chunk after a block-wide reduction of the
+//              chunk sums before it, giving cell_start; counters are zeroed;
+//   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary);
+//   gather  -- each particle's final place is cell_start + its rank by
+//              previous index among the cell's members, so the order inside a
+//              cell is the previous array order whatever the atomics did.
+#include "dpd_internal.hpp"
+
+namespace dpd {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cell_coord(float x, int L)
+{
+    int c = (int)x;                 // x >= 0 after the wrap: truncation is floor
+    c = c < 0 ? 0 : c;
+    return c > L - 1 ? L - 1 : c;
+}
+
+__device__ __forceinline__ int cell_of(float x, float y, float z, int Lx, int Ly, int Lz)
+{
+    return cell_coord(x, Lx) + Lx * (cell_coord(y, Ly) + Ly * cell_coord(z, Lz));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order (lane tree inside each wave, then waves in
+// index order).  All threads of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch /* >= blockDim/64 */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    T t = T(0);
+    for (int w = 0; w < nw; ++w) t += scratch[w];
+    return t;
+}
+
+// Inclusive scan inside a wave of 64.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int* p, int value, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+// Load n rows (id order) of positions and velocities, round positions to the
+// grid q and flag rows outside [0, L) or non-finite.
+__global__ void k_load_state(const float* __restrict__ pos3, const float* __restrict__ vel3, int n,
+                             float4* __restrict__ pos, float4* __restrict__ vel, float q, float inv_q,
+                             float Lx, float Ly, float Lz, int* bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = pos3[3 * i], y = pos3[3 * i + 1], z = pos3[3 * i + 2];
+    const float vx = vel3[3 * i], vy = vel3[3 * i + 1], vz = vel3[3 * i + 2];
+    const bool ok = (x >= 0.0f && x < Lx) && (y >= 0.0f && y < Ly) && (z >= 0.0f && z < Lz) &&
+                    isfinite(vx) && isfinite(vy) && isfinite(vz);
+    if (!ok) {
+        atomicOr(bad, 1);
+        x = y = z = 0.0f;
+    }
+    x = rintf(x * inv_q) * q;
+    y = rintf(y * inv_q) * q;
+    z = rintf(z * inv_q) * q;
+    if (x >= Lx) x -= Lx;
+    if (y >= Ly) y -= Ly;
+    if (z >= Lz) z -= Lz;
+    pos[i] = make_float4(x, y, z, __int_as_float(i));
+    vel[i] = make_float4(vx, vy, vz, 0.0f);
+}
+
+hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4* pos, float4* vel, float q,
+                             float inv_q, const float* L, int* bad, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_load_state, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos3, vel3, n, pos,
+                       vel, q, inv_q, L[0], L[1], L[2], bad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+__global__ void k_keys(const float4* __restrict__ pos, int n, int Lx, int Ly, int Lz, int* __restrict__ count,
+                       int2* __restrict__ keyslot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = pos[i];
+    const int c = cell_of(p.x, p.y, p.z, Lx, Ly, Lz);
+    keyslot[i] = make_int2(c, atomicAdd(&count[c], 1));
+}
+
+hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, n, cells[0], cells[1],
+                       cells[2], count, keyslot);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(const int* __restrict__ count, int nc, int* __restrict__ bsum)
+{
+    __shared__ int scratch[kBlock / 64];
+    const int base = blockIdx.x * kScanChunk;
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanChunk / kBlock; ++k) {
+        const int c = base + k * kBlock + threadIdx.x;
+        if (c < nc) v += count[c];
+    }
+    v = block_sum(v, scratch);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan(int* __restrict__ count, int nc, const int* __restrict__ bsum,
+                                                 int n, int* __restrict__ cell_start)
+{
+    constexpr int per = kScanChunk / kBlock;   // 8 consecutive cells per thread
+    __shared__ int scratch[kBlock / 64];
+    __shared__ int wtot[kBlock / 64];
+    // prefix of this chunk: sum of the chunk sums before it
+    int pre = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) pre += bsum[k];
+    pre = block_sum(pre, scratch);
+
+    const int c0 = blockIdx.x * kScanChunk + threadIdx.x * per;
+    int v[per];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        v[k] = (c0 + k < nc) ? count[c0 + k] : 0;
+        tsum += v[k];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int incl = wave_incl_scan(tsum);
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wtot[w];
+    int run = pre + wpre + incl - tsum;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        if (c0 + k < nc) {
+            cell_start[c0 + k] = run;
+            count[c0 + k] = 0;
+        }
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell_start[nc] = n;
+}
+
+__global__ void k_scatter(const int2* __restrict__ keyslot, const int* __restrict__ cell_start, int n,
+                          int* __restrict__ perm)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int2 ks = keyslot[i];
+    perm[cell_start[ks.x] + ks.y] = i;
+}
+
+__global__ void k_gather(const int* __restrict__ perm, const int2* __restrict__ keyslot,
+                         const int* __restrict__ cell_start, const float4* __restrict__ pos_in,
+                         const float4* __restrict__ vel_in, int n, float4* __restrict__ pos_out,
+                         float4* __restrict__ vel_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = perm[p];
+    const int c = keyslot[i].x;
+    const int s = cell_start[c], e = cell_start[c + 1];
+    int rank = 0;
+    for (int t = s; t < e; ++t) rank += perm[t] < i;
+    pos_out[s + rank] = pos_in[i];
+    vel_out[s + rank] = vel_in[i];
+}
+
+hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* vel_in, int n, int nc, int* count,
+                      int* bsum, int* cell_start, int* perm, float4* pos_out, float4* vel_out, hipStream_t s)
+{
+    const int nchunks = (nc + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_chunk_sums, dim3(nchunks), dim3(kBlock), 0, s, count, nc, bsum);
+    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(kBlock), 0, s, count, nc, bsum, n, cell_start);
+    if (n > 0) {
+        const dim3 g((n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_scatter, g, dim3(kBlock), 0, s, keyslot, cell_start, n, perm);
+        hipLaunchKernelGGL(k_gather, g, dim3(kBlock), 0, s, perm, keyslot, cell_start, pos_in, vel_in, n,
+                           pos_out, vel_out);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pair forces: reference gather form (one thread per particle, all 27 cells)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ pos,
+                                                         const float4* __restrict__ vel,
+                                                         const int* __restrict__ cell_start, int n, ForceConst fc,
+                                                         const unsigned long long* __restrict__ step_ptr,
+                                                         float4* __restrict__ force, int* __restrict__ nonfinite)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t step = (uint32_t)(*step_ptr);
+    const float4 pi = pos[i], vi = vel[i];
+    const uint32_t id_i = __float_as_uint(pi.w);
+    const int Lx = fc.cells[0], Ly = fc.cells[1], Lz = fc.cells[2];
+    const int cx = cell_coord(pi.x, Lx), cy = cell_coord(pi.y, Ly), cz = cell_coord(pi.z, Lz);
+    long long ax = 0, ay = 0, az = 0;
+    bool bad = false;
+    for (int dz = -1; dz <= 1; ++dz) {
+        int nz = cz + dz;
+        float sz = 0.0f;
+        if (nz < 0) { nz += Lz; sz = -fc.L[2]; }
+        else if (nz >= Lz) { nz -= Lz; sz = fc.L[2]; }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int ny = cy + dy;
+            float sy = 0.0f;
+            if (ny < 0) { ny += Ly; sy = -fc.L[1]; }
+            else if (ny >= Ly) { ny -= Ly; sy = fc.L[1]; }
+            for (int dx = -1; dx <= 1; ++dx) {
+                int nx = cx + dx;
+                float sx = 0.0f;
+                if (nx < 0) { nx += Lx; sx = -fc.L[0]; }
+                else if (nx >= Lx) { nx -= Lx; sx = fc.L[0]; }
+                const int cell = nx + Lx * (ny + Ly * nz);
+                const int s = cell_start[cell], e = cell_start[cell + 1];
+                for (int j = s; j < e; ++j) {
+                    if (j == i) continue;
+                    const float4 pj = pos[j];
+                    const float dxx = pi.x - (pj.x + sx);
+                    const float dyy = pi.y - (pj.y + sy);
+                    const float dzz = pi.z - (pj.z + sz);
+                    const float r2 = dist2(dxx, dyy, dzz);
+                    if (!(r2 < 1.0f) || r2 == 0.0f) continue;
+                    const float4 vj = vel[j];
+                    const float xi = pair_xi(id_i, __float_as_uint(pj.w), step, fc.pc.k0, fc.pc.k1);
+                    float rinv;
+                    const float fs = pair_scalar(r2, dxx, dyy, dzz, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, rinv,
+                                                 xi, fc.pc);
+                    const float Fx = fs * (dxx * rinv), Fy = fs * (dyy * rinv), Fz = fs * (dzz * rinv);
+                    if (fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit) {
+                        ax += fx_of(Fx);
+                        ay += fx_of(Fy);
+                        az += fx_of(Fz);
+                    } else {
+                        bad = true;
+                    }
+                }
+            }
+        }
+    }
+    double f[3] = {(double)ax * kFxInv, (double)ay * kFxInv, (double)az * kFxInv};
+    if (fc.body_f != 0.0f) {
+        const float g = fc.grad_axis == 0 ? pi.x : (fc.grad_axis == 1 ? pi.y : pi.z);
+        f[fc.flow_axis] += (double)(g <= fc.half_grad ? -fc.body_f : fc.body_f);
+    }
+    force[i] = make_float4((float)f[0], (float)f[1], (float)f[2], 0.0f);
+    if (bad) atomicOr(nonfinite, 1);
+}
+
+hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
+                               const unsigned long long* step, float4* force, int* nonfinite, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_force_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, cell_start, n,
+                       fc, step, force, nonfinite);
+    return hipGetLastError();
+}
+
+// Conservative virial sum_{i<j} r_ij . F^C_ij = sum_i sum_{j != i} a w r / 2,
+// per particle in FP64, then added as fixed point (order-independent).
+__global__ __launch_bounds__(kBlock) void k_virial(const float4* __restrict__ pos, const int* __restrict__ cell_start,
+                                                   int n, ForceConst fc, DevStats* st)
+{
+    __shared__ long long scratch[kBlock / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (i < n) {
+        const float4 pi = pos[i];
+        const int Lx = fc.cells[0], Ly = fc.cells[1], Lz = fc.cells[2];
+        const int cx = cell_coord(pi.x, Lx), cy = cell_coord(pi.y, Ly), cz = cell_coord(pi.z, Lz);
+        for (int dz = -1; dz <= 1; ++dz) {
+            int nz = cz + dz;
+            float sz = 0.0f;
+            if (nz < 0) { nz += Lz; sz = -fc.L[2]; } else if (nz >= Lz) { nz -= Lz; sz = fc.L[2]; }
+            for (int dy = -1; dy <= 1; ++dy) {
+                int ny = cy + dy;
+                float sy = 0.0f;
+                if (ny < 0) { ny += Ly; sy = -fc.L[1]; } else if (ny >= Ly) { ny -= Ly; sy = fc.L[1]; }
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int nx = cx + dx;
+                    float sx = 0.0f;
+                    if (nx < 0) { nx += Lx; sx = -fc.L[0]; } else if (nx >= Lx) { nx -= Lx; sx = fc.L[0]; }
+                    const int cell = nx + Lx * (ny + Ly * nz);
+                    for (int j = cell_start[cell]; j < cell_start[cell + 1]; ++j) {
+                        if (j == i) continue;
+                        const float4 pj = pos[j];
+                        const double ddx = (double)(pi.x - (pj.x + sx));
+                        const double ddy = (double)(pi.y - (pj.y + sy));
+                        const double ddz = (double)(pi.z - (pj.z + sz));
+                        const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                        if (!(r2 < 1.0) || r2 == 0.0) continue;
+                        const double r = sqrt(r2);
+                        acc += 0.5 * (double)fc.pc.a * (1.0 - r) * r;
+                    }
+                }
+            }
+        }
+    }
+    long long v = (long long)llrint(acc * kVirScale);
+    v = block_sum(v, scratch);
+    if (threadIdx.x == 0 && v != 0) atomicAdd((unsigned long long*)&st->virial_fx, (unsigned long long)v);
+}
+
+hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const ForceConst& fc, DevStats* st,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_virial, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, cell_start, n, fc, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused velocity-Verlet + next keys + FP64 reductions
+// ---------------------------------------------------------------------------
+constexpr int kLdsBins = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__ pos_s, const float4* __restrict__ vel_s,
+                                                      const float4* __restrict__ force, int n, StepConst sc,
+                                                      float4* __restrict__ pos_a, float4* __restrict__ vel_a,
+                                                      int* __restrict__ count, int2* __restrict__ keyslot,
+                                                      double* __restrict__ partials, long long* __restrict__ profile,
+                                                      DevStats* st)
+{
+    __shared__ long long s_psum[kLdsBins];
+    __shared__ int s_pcnt[kLdsBins];
+    __shared__ double s_red[kBlock / 64];
+    __shared__ int s_last;
+    const bool lds_prof = sc.nbins > 0 && sc.nbins <= kLdsBins;
+    if (lds_prof)
+        for (int b = threadIdx.x; b < sc.nbins; b += kBlock) { s_psum[b] = 0; s_pcnt[b] = 0; }
+    __syncthreads();
+
+    double m[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool bad = false, esc = false;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const float4 x = pos_s[i], v = vel_s[i], f = force[i];
+        const float vcx = fmaf(f.x, sc.half_dtm, v.x), vcy = fmaf(f.y, sc.half_dtm, v.y),
+                    vcz = fmaf(f.z, sc.half_dtm, v.z);
+        const float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
+        float nx = fmaf(vx, sc.dt, x.x), ny = fmaf(vy, sc.dt, x.y), nz = fmaf(vz, sc.dt, x.z);
+        const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) &&
+                         isfinite(nz);
+        if (!fin) {
+            bad = true;
+            nx = x.x; ny = x.y; nz = x.z;
+        }
+        esc |= fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
+        nx = rintf(nx * sc.inv_q) * sc.q;
+        ny = rintf(ny * sc.inv_q) * sc.q;
+        nz = rintf(nz * sc.inv_q) * sc.q;
+        if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
+        if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
+        if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
+        if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
+            esc = true;
+            nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
+            ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
+            nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
+        }
+        const int c = cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]);
+        keyslot[i] = make_int2(c, atomicAdd(&count[c], 1));
+        pos_a[i] = make_float4(nx, ny, nz, x.w);
+        vel_a[i] = make_float4(vx, vy, vz, 0.0f);
+        if (fin) {
+            m[0] += (double)vx;
+            m[1] += (double)vy;
+            m[2] += (double)vz;
+            m[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
+            m[4] += (double)vcx * vcx + (double)vcy * vcy + (double)vcz * vcz;
+            if (sc.nbins > 0) {
+                const float g = sc.grad_axis == 0 ? x.x : (sc.grad_axis == 1 ? x.y : x.z);
+                int b = (int)(g * sc.grad_scale);
+                b = b < 0 ? 0 : (b > sc.nbins - 1 ? sc.nbins - 1 : b);
+                const float vflow = sc.flow_axis == 0 ? vcx : (sc.flow_axis == 1 ? vcy : vcz);
+                const long long q = llrint((double)vflow * kProfScale);
+                if (lds_prof) {
+                    atomicAdd((unsigned long long*)&s_psum[b], (unsigned long long)q);
+                    atomicAdd(&s_pcnt[b], 1);
+                } else {
+                    atomicAdd((unsigned long long*)&profile[2 * b], (unsigned long long)q);
+                    atomicAdd((unsigned long long*)&profile[2 * b + 1], 1ull);
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(&st->nonfinite, 1);
+    if (esc) atomicOr(&st->escaped, 1);
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) {
+        const double t = block_sum(m[k], s_red);
+        if (threadIdx.x == 0) partials[blockIdx.x * kPartials + k] = t;
+    }
+    __syncthreads();
+    if (lds_prof)
+        for (int b = threadIdx.x; b < sc.nbins; b += kBlock)
+            if (s_pcnt[b]) {
+                atomicAdd((unsigned long long*)&profile[2 * b], (unsigned long long)s_psum[b]);
+                atomicAdd((unsigned long long*)&profile[2 * b + 1], (unsigned long long)s_pcnt[b]);
+            }
+
+    // The last block to finish folds the per-block partials in block order.
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&st->ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double tot[kPartials];
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+            t += __builtin_nontemporal_load(&partials[b * kPartials + k]);
+        tot[k] = block_sum(t, s_red);
+    }
+    if (threadIdx.x == 0) {
+        const double mass = sc.mass;
+        const double ke_half = 0.5 * mass * tot[3];
+        const double ke_c = 0.5 * mass * tot[4];
+        const double kT_c = 2.0 * ke_c * sc.inv_dof;
+        const long long vfx = __hip_atomic_exchange(&st->virial_fx, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double vir = (double)vfx / kVirScale;
+        const double press = sc.rho * kT_c + vir * sc.inv_vol / 3.0;
+        st->last[0] = mass * tot[0];
+        st->last[1] = mass * tot[1];
+        st->last[2] = mass * tot[2];
+        st->last[3] = ke_half;
+        st->last[4] = ke_c;
+        st->last_kT_centred = kT_c;
+        st->last_virial = vir;
+        st->last_pressure = press;
+        st->sum_kT_centred += kT_c;
+        st->sum_pressure += press;
+        st->sum_momentum[0] += mass * tot[0];
+        st->sum_momentum[1] += mass * tot[1];
+        st->sum_momentum[2] += mass * tot[2];
+        st->nsamples += 1;
+        st->step += 1;
+        st->ticket = 0;
+        __threadfence();
+    }
+}
+
+hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const float4* force, int n, const StepConst& sc,
+                            float4* pos_a, float4* vel_a, int* count, int2* keyslot, double* partials,
+                            long long* profile, DevStats* st, hipStream_t s)
+{
+    int blocks = (n + kBlock - 1) / kBlock;
+    if (blocks < 1) blocks = 1;
+    if (blocks > kIntegrateMaxBlocks) blocks = kIntegrateMaxBlocks;
+    hipLaunchKernelGGL(k_integrate, dim3(blocks), dim3(kBlock), 0, s, pos_s, vel_s, force, n, sc, pos_a, vel_a, count,
+                       keyslot, partials, profile, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// read-back: rows in id order
+// ---------------------------------------------------------------------------
+__global__ void k_to_rows(const float4* __restrict__ src, const float4* __restrict__ sub, float sub_scale,
+                          const float4* __restrict__ idsrc, int n, float* __restrict__ out3)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 v = src[i];
+    if (sub) {
+        const float4 u = sub[i];
+        v.x = fmaf(u.x, sub_scale, v.x);
+        v.y = fmaf(u.y, sub_scale, v.y);
+        v.z = fmaf(u.z, sub_scale, v.z);
+    }
+    const int id = __float_as_int(idsrc[i].w);
+    if (id < 0 || id >= n) return;
+    out3[3 * id] = v.x;
+    out3[3 * id + 1] = v.y;
+    out3[3 * id + 2] = v.z;
+}
+
+hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,
+                          float* out3, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_rows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, sub, sub_scale, idsrc, n,
+                       out3);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// random-term diagnostics
+// ---------------------------------------------------------------------------
+__global__ void k_philox(const uint32_t* __restrict__ ctr4, const uint32_t* __restrict__ key2, int64_t n,
+                         uint32_t* __restrict__ out4)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 c = make_uint4(ctr4[4 * i], ctr4[4 * i + 1], ctr4[4 * i + 2], ctr4[4 * i + 3]);
+    const uint4 w = philox10(c, key2[2 * i], key2[2 * i + 1]);
+    out4[4 * i] = w.x;
+    out4[4 * i + 1] = w.y;
+    out4[4 * i + 2] = w.z;
+    out4[4 * i + 3] = w.w;
+}
+
+hipError_t launch_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, ctr4, key2, n, out4);
+    return hipGetLastError();
+}
+
+__global__ void k_box_muller(const uint32_t* __restrict__ w0, const uint32_t* __restrict__ w1, int64_t n,
+                             float* __restrict__ xi)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) xi[i] = box_muller(w0[i], w1[i]);
+}
+
+hipError_t launch_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_box_muller, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, w0, w1, n, xi);
+    return hipGetLastError();
+}
+
+}  // namespace dpd

@@ -1,0 +1,282 @@
+"""Python binding of the C-ABI in include/dpd.h (argument marshalling only).
+
+Every step of the DPD path runs in the HIP library libdpd.so; this module
+allocates the workspace as a torch CUDA tensor, passes torch's current
+stream, and converts arrays.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, EAGAIN, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
+HOST, DEVICE = 0, 1
+POS, VEL, VEL_CENTRED, FORCE = 0, 1, 2, 3
+FLAG_VIRIAL = 1
+
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE",
+          EAGAIN: "EAGAIN", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND"}
+
+
+class DPDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32), ("n", ctypes.c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
+                ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32),
+                ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("momentum", ctypes.c_double * 3), ("ke_half", ctypes.c_double),
+                ("ke_centred", ctypes.c_double), ("kT_centred", ctypes.c_double),
+                ("virial", ctypes.c_double), ("pressure", ctypes.c_double),
+                ("sum_kT_centred", ctypes.c_double), ("sum_pressure", ctypes.c_double),
+                ("sum_momentum", ctypes.c_double * 3), ("nsamples", ctypes.c_uint64),
+                ("step", ctypes.c_uint64), ("nonfinite", ctypes.c_int32), ("escaped", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"momentum": np.array(self.momentum), "ke_half": self.ke_half, "ke_centred": self.ke_centred,
+                "kT_centred": self.kT_centred, "virial": self.virial, "pressure": self.pressure,
+                "sum_kT_centred": self.sum_kT_centred, "sum_pressure": self.sum_pressure,
+                "sum_momentum": np.array(self.sum_momentum), "nsamples": int(self.nsamples),
+                "step": int(self.step), "nonfinite": int(self.nonfinite), "escaped": int(self.escaped)}
+
+
+# Every symbol include/dpd.h declares, with its ctypes signature.
+_VP, _I64 = ctypes.c_void_p, ctypes.c_int64
+SIGNATURES = {
+    "dpd_position_grid": ([ctypes.POINTER(Geom), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "dpd_workspace_bytes": ([ctypes.POINTER(Geom), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "dpd_create": ([ctypes.POINTER(Geom), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "dpd_set_params": ([_VP, ctypes.POINTER(Params)], ctypes.c_int),
+    "dpd_set_seed": ([_VP, ctypes.c_uint64], ctypes.c_int),
+    "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
+    "dpd_build_cells": ([_VP], ctypes.c_int),
+    "dpd_step": ([_VP, _I64], ctypes.c_int),
+    "dpd_read": ([_VP, ctypes.c_int, _VP, ctypes.c_int], ctypes.c_int),
+    "dpd_read_raw": ([_VP, _VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
+    "dpd_get_stats": ([_VP, ctypes.POINTER(Stats)], ctypes.c_int),
+    "dpd_get_profile": ([_VP, _VP, _VP, ctypes.c_int32], ctypes.c_int),
+    "dpd_reset_accumulators": ([_VP], ctypes.c_int),
+    "dpd_destroy": ([_VP], ctypes.c_int),
+    "dpd_profile_steps": ([_VP, _I64, _VP], ctypes.c_int),
+    "dpd_last_error": ([], ctypes.c_char_p),
+    "dpd_philox": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "dpd_box_muller": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdpd.so (never builds; build with paper_1911_04712_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1911_04712_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DPDError(rc, lib().dpd_last_error().decode(errors="replace"))
+    return rc
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the DPD library needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream_ptr(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_geom(cells, n):
+    return Geom((ctypes.c_int32 * 3)(*[int(c) for c in cells]), 0, int(n))
+
+
+def position_grid(cells, n=0):
+    q = ctypes.c_double()
+    _check(lib().dpd_position_grid(ctypes.byref(make_geom(cells, n)), ctypes.byref(q)))
+    return q.value
+
+
+def workspace_bytes(cells, n):
+    b = ctypes.c_size_t()
+    _check(lib().dpd_workspace_bytes(ctypes.byref(make_geom(cells, n)), ctypes.byref(b)))
+    return b.value
+
+
+def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1,
+                profile_bins=0, flags=0):
+    return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f), int(flow_axis),
+                  int(grad_axis), int(profile_bins), int(flags))
+
+
+def _as_arg(arr, dtype, shape_tail):
+    """(pointer, where, keepalive) for a numpy array or a torch CUDA tensor."""
+    try:
+        import torch
+        if isinstance(arr, torch.Tensor):
+            if not arr.is_cuda:
+                arr = arr.numpy()
+            else:
+                t = arr.contiguous()
+                return ctypes.c_void_p(t.data_ptr()), DEVICE, t
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(arr, dtype=dtype)
+    if shape_tail is not None:
+        a = a.reshape(-1, shape_tail)
+    return a.ctypes.data_as(ctypes.c_void_p), HOST, a
+
+
+class Box:
+    """One periodic DPD box resident in a torch-allocated HBM workspace."""
+
+    def __init__(self, cells, n, params=None, seed=None, device="cuda"):
+        torch = _torch()
+        self.cells = tuple(int(c) for c in cells)
+        self.n = int(n)
+        self.ws_bytes = workspace_bytes(self.cells, self.n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self._h = ctypes.c_void_p()
+        _check(lib().dpd_create(ctypes.byref(make_geom(self.cells, self.n)), ctypes.c_void_p(self.ws.data_ptr()),
+                                self.ws_bytes, _stream_ptr(torch), ctypes.byref(self._h)))
+        self.params = None
+        if params is not None:
+            self.set_params(params)
+        if seed is not None:
+            self.set_seed(seed)
+
+    # -- setup --------------------------------------------------------------
+    def set_params(self, params=None, **kw):
+        p = params if isinstance(params, Params) else make_params(**(params or {}), **kw)
+        _check(lib().dpd_set_params(self._h, ctypes.byref(p)))
+        self.params = p
+
+    def set_seed(self, seed):
+        _check(lib().dpd_set_seed(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+    def set_state(self, pos, vel):
+        pp, wp, k1 = _as_arg(pos, np.float32, 3)
+        vp, wv, k2 = _as_arg(vel, np.float32, 3)
+        if wp != wv:
+            raise ValueError("pos and vel must both be host arrays or both device tensors")
+        _check(lib().dpd_set_state(self._h, pp, vp, wp))
+
+    # -- stepping -----------------------------------------------------------
+    def build_cells(self):
+        _check(lib().dpd_build_cells(self._h))
+
+    def step(self, nsteps=1):
+        _check(lib().dpd_step(self._h, int(nsteps)))
+
+    def profile_steps(self, nsteps):
+        """Mean device ms per step of each stage (bin, force, virial, integrate),
+        timed with HIP events around eager launches."""
+        ms = np.zeros(4)
+        _check(lib().dpd_profile_steps(self._h, int(nsteps), ms.ctypes.data_as(ctypes.c_void_p)))
+        return dict(zip(("bin", "force", "virial", "integrate"), ms.tolist()))
+
+    # -- reads --------------------------------------------------------------
+    def read(self, what=POS, out=None):
+        """n x 3 float32 rows in id order (numpy, or into a CUDA tensor `out`)."""
+        if out is not None:
+            op, w, keep = _as_arg(out, np.float32, None)
+            _check(lib().dpd_read(self._h, int(what), op, w))
+            return out
+        a = np.empty((self.n, 3), dtype=np.float32)
+        _check(lib().dpd_read(self._h, int(what), a.ctypes.data_as(ctypes.c_void_p), HOST))
+        return a
+
+    def read_raw(self):
+        """(pos4, vel4, cell_start) of the last binning, in cell order."""
+        nc = self.cells[0] * self.cells[1] * self.cells[2]
+        p4 = np.empty((self.n, 4), dtype=np.float32)
+        v4 = np.empty((self.n, 4), dtype=np.float32)
+        cs = np.empty(nc + 1, dtype=np.int32)
+        _check(lib().dpd_read_raw(self._h, p4.ctypes.data_as(ctypes.c_void_p), v4.ctypes.data_as(ctypes.c_void_p),
+                                  cs.ctypes.data_as(ctypes.c_void_p), HOST))
+        return p4, v4, cs
+
+    def stats(self, allow_nonfinite=False):
+        s = Stats()
+        rc = lib().dpd_get_stats(self._h, ctypes.byref(s))
+        if rc != OK and not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc)
+        return s.as_dict()
+
+    def profile(self):
+        nb = int(self.params.profile_bins)
+        sv = np.zeros(nb)
+        cn = np.zeros(nb)
+        _check(lib().dpd_get_profile(self._h, sv.ctypes.data_as(ctypes.c_void_p), cn.ctypes.data_as(ctypes.c_void_p),
+                                     nb))
+        return sv, cn
+
+    def reset_accumulators(self):
+        _check(lib().dpd_reset_accumulators(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dpd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def philox(ctr4, key2):
+    """Philox4x32-10 words computed on the GPU (uint32 arrays n x 4, n x 2)."""
+    torch = _torch()
+    c = torch.as_tensor(np.ascontiguousarray(ctr4, dtype=np.uint32).view(np.int32), device="cuda")
+    k = torch.as_tensor(np.ascontiguousarray(key2, dtype=np.uint32).view(np.int32), device="cuda")
+    n = c.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    _check(lib().dpd_philox(ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(k.data_ptr()), n,
+                            ctypes.c_void_p(out.data_ptr()), DEVICE, _stream_ptr(torch)))
+    return out.cpu().numpy().view(np.uint32)
+
+
+def box_muller(w0, w1):
+    """FP32 Box-Muller of the force kernel, on the GPU."""
+    torch = _torch()
+    a = torch.as_tensor(np.ascontiguousarray(w0, dtype=np.uint32).view(np.int32), device="cuda")
+    b = torch.as_tensor(np.ascontiguousarray(w1, dtype=np.uint32).view(np.int32), device="cuda")
+    out = torch.empty(a.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().dpd_box_muller(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), a.shape[0],
+                                ctypes.c_void_p(out.data_ptr()), DEVICE, _stream_ptr(torch)))
+    return out.cpu().numpy()

@@ -1,0 +1,106 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/dpd.h declares, its structs match the header's
+layout, and host-only calls validate their arguments."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1911_04712_amd import dpd, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpd_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dpd.LIB_PATH):
+        pytest.fail("libdpd.so is not built (run __graft_entry__.build())")
+    return dpd.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "dpd_step" in names and "dpd_create" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", dpd.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (dpd_[a-z_0-9]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert sorted(dpd.SIGNATURES) == names
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "dpd.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(dpd_geom), sizeof(dpd_params), sizeof(dpd_stats));
+  printf("%zu %zu %zu %zu\\n", offsetof(dpd_params, flow_axis), offsetof(dpd_params, flags),
+         offsetof(dpd_stats, nsamples), offsetof(dpd_stats, escaped));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
+    sizes = [int(x) for x in a.split()]
+    offs = [int(x) for x in b.split()]
+    assert sizes == [ctypes.sizeof(dpd.Geom), ctypes.sizeof(dpd.Params), ctypes.sizeof(dpd.Stats)]
+    assert offs == [dpd.Params.flow_axis.offset, dpd.Params.flags.offset, dpd.Stats.nsamples.offset,
+                    dpd.Stats.escaped.offset]
+
+
+@pytest.mark.parametrize("cells", [(3, 3, 3), (8, 8, 8), (48, 48, 48), (192, 96, 96), (7, 64, 5), (127, 3, 3)])
+def test_position_grid_matches_input_generator(lib, cells):
+    assert dpd.position_grid(cells) == inputs.position_grid(cells)
+    q = dpd.position_grid(cells)
+    L = max(cells)
+    # q is the FP32 spacing at L: L + q is the next float above L
+    assert float(np.float32(L) + np.float32(q)) == L + q
+    assert float(np.nextafter(np.float32(L), np.float32(2 * L))) == L + q
+
+
+def test_workspace_bytes_and_validation(lib):
+    small = dpd.workspace_bytes((8, 8, 8), 1536)
+    big = dpd.workspace_bytes((48, 48, 48), 331776)
+    assert 0 < small < big
+    assert big >= 331776 * 100
+    for bad in [((2, 8, 8), 10), ((8, 8, 8), -1), ((8, 8, 8), 2 ** 31), ((0, 0, 0), 0)]:
+        with pytest.raises(dpd.DPDError) as e:
+            dpd.workspace_bytes(*bad)
+        assert e.value.code == dpd.EINVAL
+    assert b"invalid geometry" in lib.dpd_last_error()
+
+
+def test_create_rejects_bad_workspace_before_any_device_call(lib):
+    g = dpd.make_geom((8, 8, 8), 100)
+    h = ctypes.c_void_p()
+    assert lib.dpd_create(ctypes.byref(g), None, 1 << 20, None, ctypes.byref(h)) == dpd.EINVAL
+    assert lib.dpd_create(ctypes.byref(g), ctypes.c_void_p(256 * 3 + 1), 1 << 20, None, ctypes.byref(h)) == dpd.EINVAL
+    assert lib.dpd_create(ctypes.byref(g), ctypes.c_void_p(1 << 20), 1024, None, ctypes.byref(h)) == dpd.ENOMEM
+    assert h.value is None
+    assert lib.dpd_destroy(None) == dpd.OK
+
+
+def test_null_box_calls_fail_cleanly(lib):
+    p = dpd.make_params()
+    assert lib.dpd_set_params(None, ctypes.byref(p)) == dpd.EINVAL
+    assert lib.dpd_step(None, 1) == dpd.EINVAL
+    assert lib.dpd_set_seed(None, 1) == dpd.EINVAL
+    s = dpd.Stats()
+    assert lib.dpd_get_stats(None, ctypes.byref(s)) == dpd.EINVAL
+    assert lib.dpd_philox(None, None, 4, None, dpd.HOST, None) == dpd.EINVAL

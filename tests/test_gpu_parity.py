@@ -1,0 +1,398 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle on the
+same seeded inputs.
+
+Bars (written at each test):
+  - integer work (cell lists, Philox words, ids): bit-exact;
+  - forces after one step: |f_gpu - f_orc| <= 1e-5 * S_i per particle, with
+    S_i the oracle's sum of the magnitudes of all force terms on i;
+  - one-step state: |dv| <= dt * 1e-5 * S_i + 4 ulp(v), |dx| <= 2 q + dt |dv|
+    (q the position grid);
+  - statistics over long runs within three combined standard errors.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_04712_amd import dpd, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _box(cells, pos, vel, params, seed):
+    b = dpd.Box(cells, len(pos), params=params, seed=seed)
+    b.set_state(pos, vel)
+    return b
+
+
+def _orc_params(p):
+    return oracle.make_params(a=p.a, gamma=p.gamma, kT=p.kT, dt=p.dt, mass=p.mass, body_f=p.body_f,
+                              flow_axis=p.flow_axis, grad_axis=p.grad_axis)
+
+
+def _force_check(f_gpu, f_orc, s_orc, label):
+    err = np.linalg.norm(f_gpu.astype(np.float64) - f_orc, axis=1)
+    worst = np.max(err / np.maximum(s_orc, 1e-300)) if len(err) else 0.0
+    _say(f"[{label}] max |df|/S = {worst:.3e}")
+    assert np.all(err <= TOL_F * s_orc + 1e-30), (label, worst)
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# random term
+# ---------------------------------------------------------------------------
+
+def test_philox_words_bit_exact():
+    rng = np.random.default_rng(100)
+    n = 200_000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[:, 3][: n // 2] = 0
+    got = dpd.philox(ctr, key)
+    ref = np.vstack([oracle.philox4x32_10(ctr[k:k + 1], key[k]) for k in range(0, 2000)])
+    np.testing.assert_array_equal(got[:2000], ref)
+    # bulk: same key for a batch so the oracle call is vectorised
+    key1 = np.tile(key[0], (n, 1))
+    np.testing.assert_array_equal(dpd.philox(ctr, key1), oracle.philox4x32_10(ctr, key[0]))
+
+
+def test_box_muller_exhaustive_24bit_maps():
+    """All 2^24 values of each uniform: u1 with u2 = 0 (cos = 1), and u2 with
+    u1 = 1/2 (radius sqrt(2 ln 2)).  FP32 GPU vs FP64 oracle."""
+    k = np.arange(1 << 24, dtype=np.uint32) << 8
+    zeros = np.zeros_like(k)
+    half = np.full_like(k, ((1 << 23) - 1) << 8)
+    g1 = dpd.box_muller(k, zeros).astype(np.float64)
+    r1 = oracle.box_muller_batch(k, zeros)
+    g2 = dpd.box_muller(half, k).astype(np.float64)
+    r2 = oracle.box_muller_batch(half, k)
+    e1, e2 = np.abs(g1 - r1), np.abs(g2 - r2)
+    rel1 = e1 / np.maximum(np.abs(r1), 1e-30)
+    _say(f"radius map: max abs err {e1.max():.3e}, max rel err {rel1[r1 > 1e-3].max():.3e}; "
+         f"cos map: max abs err {e2.max():.3e}")
+    assert e1.max() < 4e-6 and e2.max() < 4e-6
+
+
+# ---------------------------------------------------------------------------
+# cell lists: bit-exact against the oracle's stable counting sort
+# ---------------------------------------------------------------------------
+
+def _check_cells(cells, pos, label):
+    vel = np.zeros_like(pos)
+    b = dpd.Box(cells, len(pos), params=dpd.make_params(), seed=0)
+    b.set_state(pos, vel)
+    b.build_cells()
+    p4, v4, cs = b.read_raw()
+    order, start = oracle.bin_cells(pos, cells)
+    np.testing.assert_array_equal(cs, start, err_msg=label)
+    ids = p4[:, 3].view(np.int32)
+    np.testing.assert_array_equal(ids, order.astype(np.int32), err_msg=label)
+    np.testing.assert_array_equal(p4[:, :3], pos[order], err_msg=label)
+    b.close()
+
+
+@pytest.mark.parametrize("cells,n,seed", [((8, 8, 8), 1536, 0), ((3, 3, 3), 81, 1), ((5, 7, 3), 400, 2),
+                                          ((48, 48, 48), 331776, 3), ((3, 3, 3), 1, 4), ((4, 4, 4), 0, 5)])
+def test_cell_list_bit_exact_uniform(cells, n, seed):
+    pos, _ = inputs.uniform_state(cells, n=n, seed=seed)
+    _check_cells(cells, pos, f"uniform {cells} n={n}")
+
+
+@pytest.mark.parametrize("cells,n,seed", [((6, 5, 4), 700, 6), ((9, 9, 9), 4000, 7)])
+def test_cell_list_bit_exact_faces(cells, n, seed):
+    pos, _ = inputs.face_state(cells, n, seed=seed)
+    _check_cells(cells, pos, f"faces {cells}")
+
+
+def test_cell_list_bit_exact_clumped():
+    pos, _ = inputs.clumped_state((8, 8, 8), 600, centre=(4.0, 4.0, 4.0), radius=0.9, seed=8)
+    _check_cells((8, 8, 8), pos, "clumped")
+
+
+def test_cell_list_stays_stable_while_stepping():
+    """Over 30 steps each cell list is valid and keeps, inside every cell, the
+    order the particles had after the previous step."""
+    cells = (6, 6, 6)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=9)
+    b = _box(cells, pos, vel, dpd.make_params(), 9)
+    b.step(1)
+    prev_ids = b.read_raw()[0][:, 3].view(np.int32).copy()
+    for _ in range(30):
+        b.step(1)
+        p4, _, cs = b.read_raw()
+        ids = p4[:, 3].view(np.int32)
+        where = np.empty(len(ids), dtype=np.int64)
+        where[prev_ids] = np.arange(len(ids))
+        c = np.floor(p4[:, :3].astype(np.float64)).astype(np.int64)
+        key = c[:, 0] + 6 * (c[:, 1] + 6 * c[:, 2])
+        assert np.all(np.diff(key) >= 0)
+        assert np.all(np.diff(cs) >= 0) and cs[-1] == len(ids)
+        for k in range(216):
+            seg = ids[cs[k]:cs[k + 1]]
+            assert np.all(key[cs[k]:cs[k + 1]] == k)
+            assert np.all(np.diff(where[seg]) > 0)
+        prev_ids = ids.copy()
+
+
+# ---------------------------------------------------------------------------
+# forces and one step
+# ---------------------------------------------------------------------------
+
+CASES = {
+    "cube8_rho3": dict(cells=(8, 8, 8), rho=3.0, p=dict(a=25.0, gamma=4.5, kT=1.0, dt=0.01), seed=0),
+    "ragged_5x7x3": dict(cells=(5, 7, 3), rho=3.0, p=dict(a=25.0, gamma=4.5, kT=1.0, dt=0.01), seed=11),
+    "rho8_poiseuille": dict(cells=(12, 10, 8), rho=8.0,
+                            p=dict(a=10.0, gamma=10.0, kT=1.0, dt=0.005, body_f=0.05, profile_bins=10), seed=2),
+    "cube3_rho8": dict(cells=(3, 3, 3), rho=8.0, p=dict(a=25.0, gamma=4.5, kT=1.0, dt=0.01), seed=12),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forces_one_step(name):
+    c = CASES[name]
+    pos, vel = inputs.uniform_state(c["cells"], density=c["rho"], seed=c["seed"])
+    params = dpd.make_params(**c["p"])
+    b = _box(c["cells"], pos, vel, params, c["seed"])
+    b.step(1)
+    f_gpu = b.read(dpd.FORCE)
+    ids = np.arange(len(pos), dtype=np.uint32)
+    f_orc, s_orc, _ = oracle.forces(pos, vel, ids, c["cells"], _orc_params(params), step=0, seed=c["seed"])
+    _force_check(f_gpu, f_orc, s_orc, name)
+
+
+def test_forces_clumped_cells():
+    cells = (8, 8, 8)
+    pos, vel = inputs.clumped_state(cells, 500, centre=(0.2, 7.9, 4.0), radius=0.8, seed=13)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    b = _box(cells, pos, vel, params, 13)
+    b.step(1)
+    ids = np.arange(len(pos), dtype=np.uint32)
+    f_orc, s_orc, _ = oracle.forces(pos, vel, ids, cells, _orc_params(params), 0, 13)
+    _force_check(b.read(dpd.FORCE), f_orc, s_orc, "clumped")
+
+
+def test_one_step_state_and_stats():
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=0)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, profile_bins=8, body_f=0.02)
+    b = _box(cells, pos, vel, params, 0)
+    b.step(1)
+    x = pos.astype(np.float64).copy()
+    v = vel.astype(np.float64).copy()
+    ids = np.arange(len(pos), dtype=np.uint32)
+    diag, ps, pc, f_orc = oracle.step(x, v, ids, cells, _orc_params(params), 0, 0, 1, nbins=8)
+    _, s_orc, _ = oracle.forces(pos, vel, ids, cells, _orc_params(params), 0, 0)
+    vg, xg = b.read(dpd.VEL).astype(np.float64), b.read(dpd.POS).astype(np.float64)
+    q = dpd.position_grid(cells)
+    dv = np.abs(vg - v)
+    tol_v = 0.01 * TOL_F * s_orc[:, None] + 4 * np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)
+    assert np.all(dv <= tol_v)
+    dx = np.abs(xg - x)
+    dx = np.minimum(dx, 8.0 - dx)                      # periodic
+    assert np.all(dx <= 2 * q + 0.01 * dv + 1e-12)
+    vc_gpu = b.read(dpd.VEL_CENTRED).astype(np.float64)
+    vc_orc = vel.astype(np.float64) + 0.5 * 0.01 * f_orc
+    assert np.all(np.abs(vc_gpu - vc_orc) <= 0.5 * tol_v + 4 * np.spacing(np.float32(8.0)))
+    st = b.stats()
+    assert st["step"] == 1 and st["nsamples"] == 1 and st["nonfinite"] == 0
+    np.testing.assert_allclose(st["momentum"], diag["momentum"][0], rtol=0, atol=1e-4)
+    assert st["ke_half"] == pytest.approx(diag["ke_half"][0], rel=1e-6)
+    assert st["ke_centred"] == pytest.approx(diag["ke_centred"][0], rel=1e-6)
+    sv, cn = b.profile()
+    np.testing.assert_array_equal(cn, pc)
+    np.testing.assert_allclose(sv, ps, rtol=0, atol=1e-4)
+
+
+def test_ten_steps_track_the_oracle():
+    """Trajectories are chaotic; over 10 steps FP32 and FP64 still agree to
+    far below the particle spacing."""
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=14)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    b = _box(cells, pos, vel, params, 14)
+    b.step(10)
+    x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    oracle.step(x, v, np.arange(len(x), dtype=np.uint32), cells, _orc_params(params), 14, 0, 10, want_diag=False)
+    dx = np.abs(b.read(dpd.POS) - x)
+    dx = np.minimum(dx, 8.0 - dx)
+    dv = np.abs(b.read(dpd.VEL) - v)
+    _say(f"10 steps: max |dx| {dx.max():.3e}, max |dv| {dv.max():.3e}")
+    assert dx.max() < 1e-3 and dv.max() < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads: sampled particles against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["cube48_rho3", "pp192x96x96_rho8"])
+def test_full_size_forces_sampled(name):
+    w = inputs.WORKLOADS[name]
+    _say(f"[{name}] generating {w.n} particles")
+    pos, vel = inputs.uniform_state(w.cells, n=w.n, kT=w.kT, seed=w.seed)
+    params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, body_f=w.body_f, profile_bins=w.profile_bins)
+    b = _box(w.cells, pos, vel, params, w.seed)
+    b.step(1)
+    f_gpu = b.read(dpd.FORCE)
+    rng = np.random.default_rng(15)
+    sample = np.sort(rng.choice(w.n, size=4000, replace=False))
+    ids = np.arange(w.n, dtype=np.uint32)
+    f_orc, s_orc, _ = oracle.forces(pos, vel, ids, w.cells, _orc_params(params), 0, w.seed, which=sample)
+    _force_check(f_gpu[sample], f_orc, s_orc, name)
+    st = b.stats()
+    assert st["nonfinite"] == 0 and st["escaped"] == 0
+    # total pair momentum: sum of forces equals the body-force sum to FP32 rounding
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# determinism, statistics, errors
+# ---------------------------------------------------------------------------
+
+def test_run_twice_bitwise_identical():
+    cells = (10, 9, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=16)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, body_f=0.05, profile_bins=9)
+    out = []
+    for _ in range(2):
+        b = _box(cells, pos, vel, params, 16)
+        b.step(57)
+        out.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE), b.stats(), b.profile()))
+        b.close()
+    for k in range(3):
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+    assert out[0][3]["ke_half"] == out[1][3]["ke_half"]
+    np.testing.assert_array_equal(out[0][4][0], out[1][4][0])
+
+
+def test_pair_forces_conserve_momentum_exactly():
+    """Fixed-point accumulation of exactly antisymmetric pair forces: the sum
+    of all pair forces is zero up to the final FP32 rounding of each force."""
+    cells = (16, 16, 16)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=17)
+    b = _box(cells, pos, vel, dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01), 17)
+    b.step(1)
+    f = b.read(dpd.FORCE).astype(np.float64)
+    tot = np.abs(f.sum(axis=0))
+    bound = np.sum(np.spacing(np.abs(f).astype(np.float32)).astype(np.float64), axis=0)
+    assert np.all(tot <= bound), (tot, bound)
+
+
+def test_equilibrium_statistics_match_oracle():
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=11)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, flags=dpd.FLAG_VIRIAL)
+    b = _box(cells, pos, vel, params, 11)
+    b.step(1000)
+    kts, prs = [], []
+    for blk in range(10):
+        b.reset_accumulators()
+        b.step(500)
+        st = b.stats()
+        kts.append(st["sum_kT_centred"] / st["nsamples"])
+        prs.append(st["sum_pressure"] / st["nsamples"])
+    kt, se_kt = np.mean(kts), np.std(kts, ddof=1) / math.sqrt(len(kts))
+    pr, se_pr = np.mean(prs), np.std(prs, ddof=1) / math.sqrt(len(prs))
+    x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    diag, _, _, _ = oracle.step(x, v, np.arange(len(x), dtype=np.uint32), cells,
+                                oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01), 11, 0, 6000)
+    okt = diag["kT_centred"][1000:].reshape(10, -1).mean(axis=1)
+    opr = diag["pressure"][1000:].reshape(10, -1).mean(axis=1)
+    _say(f"GPU kT {kt:.4f}+-{se_kt:.4f} p {pr:.3f}+-{se_pr:.3f}; oracle kT {okt.mean():.4f} p {opr.mean():.3f}")
+    assert abs(kt - 1.0) < 0.01
+    se_o = okt.std(ddof=1) / math.sqrt(10)
+    assert abs(kt - okt.mean()) < 3 * math.hypot(se_kt, se_o) + 1e-3
+    sp_o = opr.std(ddof=1) / math.sqrt(10)
+    assert abs(pr - opr.mean()) < 3 * math.hypot(se_pr, sp_o) + 0.02
+
+
+def test_poiseuille_profile_on_gpu():
+    cells = (8, 8, 8)
+    nb = 16
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=13)
+    params = dpd.make_params(a=25.0, gamma=6.75, kT=1.0, dt=0.04, body_f=0.1, profile_bins=nb)
+    b = _box(cells, pos, vel, params, 13)
+    b.step(1500)
+    prof = []
+    for blk in range(10):
+        b.reset_accumulators()
+        b.step(300)
+        sv, cn = b.profile()
+        prof.append(sv / cn)
+    prof = np.array(prof)
+    mean, err = prof.mean(axis=0), prof.std(axis=0, ddof=1) / math.sqrt(10)
+    L = 8.0
+    def shape(y0, y1):
+        yy = np.linspace(y0, y1, 201)
+        s = np.mod(yy, L / 2)
+        return np.mean(np.where(yy <= L / 2, -1.0, 1.0) * s * (L / 2 - s))
+    g = np.array([shape(i * L / nb, (i + 1) * L / nb) for i in range(nb)])
+    w = 1.0 / err ** 2
+    c = np.sum(w * g * mean) / np.sum(w * g * g)
+    eta = 3.0 * 0.1 / (2.0 * c)
+    _say(f"GPU Poiseuille eta = {eta:.3f}")
+    assert np.all(mean[: nb // 2] < 0) and np.all(mean[nb // 2:] > 0)
+    assert abs(eta - 0.91) < 0.15 * 0.91
+
+
+def test_error_paths():
+    cells = (4, 4, 4)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=18)
+    b = dpd.Box(cells, len(pos))
+    with pytest.raises(dpd.DPDError) as e:
+        b.step(1)
+    assert e.value.code == dpd.ESTATE
+    b.set_params(dpd.make_params())
+    b.set_seed(1)
+    bad = pos.copy()
+    bad[5, 1] = 4.0                                    # == L: outside [0, L)
+    with pytest.raises(dpd.DPDError) as e:
+        b.set_state(bad, vel)
+    assert e.value.code == dpd.EINVAL
+    nanv = vel.copy()
+    nanv[3, 0] = np.nan
+    with pytest.raises(dpd.DPDError) as e:
+        b.set_state(pos, nanv)
+    assert e.value.code == dpd.EINVAL
+    with pytest.raises(dpd.DPDError) as e:
+        b.read(dpd.POS)
+    assert e.value.code == dpd.ESTATE
+    for kw in [dict(dt=0.0), dict(gamma=-1.0), dict(flow_axis=1, grad_axis=1), dict(profile_bins=5000),
+               dict(kT=float("nan"))]:
+        with pytest.raises(dpd.DPDError) as e:
+            b.set_params(dpd.make_params(**kw))
+        assert e.value.code == dpd.EINVAL
+    b.set_state(pos, vel)
+    with pytest.raises(dpd.DPDError) as e:
+        b.read(dpd.FORCE)
+    assert e.value.code == dpd.ESTATE
+    # an absurd time step makes particles jump more than a cell: reported
+    b.set_params(dpd.make_params(dt=5.0))
+    b.step(2)
+    st = b.stats(allow_nonfinite=True)
+    assert st["escaped"] == 1
+    b.close()
+
+
+def test_empty_and_single_particle_boxes():
+    b = dpd.Box((3, 3, 3), 0, params=dpd.make_params(), seed=0)
+    b.set_state(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32))
+    b.step(5)
+    assert b.read(dpd.POS).shape == (0, 3)
+    assert b.stats()["step"] == 5
+    b.close()
+    pos = np.array([[1.5, 1.5, 1.5]], np.float32)
+    vel = np.array([[0.5, -0.25, 0.125]], np.float32)
+    b = dpd.Box((3, 3, 3), 1, params=dpd.make_params(dt=0.01, body_f=0.2), seed=0)
+    b.set_state(pos, vel)
+    b.step(3)
+    f = b.read(dpd.FORCE)
+    np.testing.assert_array_equal(f, [[-0.2, 0.0, 0.0]] if False else [[np.float32(-0.2), 0.0, 0.0]])
+    b.close()
