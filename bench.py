@@ -95,7 +95,7 @@ def main():
     force_bytes = n * (32.0 + 16.0) + (n / rho) * 4.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "k_force_gather", "kernel_ms": round(f_ms, 4),
+                "kernel": "k_force_tiled", "kernel_ms": round(f_ms, 4),
                 "hbm_algorithmic_GBps": round(force_bytes / (f_ms / 1e3) / 1e9, 1)}
 
     out = {"metric": "particle-steps/s DPD (1 GPU)", "value": value, "unit": "particle-steps/s", "n_gpus": 1,

@@ -79,7 +79,10 @@ enum {
 
 /* flags of dpd_params.flags */
 enum {
-    DPD_FLAG_VIRIAL = 1   /* also accumulate the conservative virial each step   */
+    DPD_FLAG_VIRIAL = 1,          /* also accumulate the conservative virial each step   */
+    DPD_FLAG_REFERENCE_FORCE = 2  /* use the one-thread-per-particle gather kernel for
+                                     the pair forces instead of the LDS tile kernel (same
+                                     bits; a reference for validation)                    */
 };
 
 typedef struct dpd_box_s* dpd_box;
@@ -144,6 +147,11 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
 
 /* Set model parameters; validated as documented at dpd_params. */
 int dpd_set_params(dpd_box box, const dpd_params* params);
+
+/* Cell-tile shape of the LDS pair-force kernel: tile[3] edges in cells
+ * (each 1..16), or {0, 0, 0} for the default chosen from the density.
+ * Results do not depend on the tile shape (bitwise). */
+int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 
 /* Set the 64-bit seed of the random term. */
 int dpd_set_seed(dpd_box box, uint64_t seed);

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdpd.so")
-SOURCES = ["dpd_kernels.hip", "dpd_capi.hip"]
+SOURCES = ["dpd_kernels.hip", "dpd_force.hip", "dpd_capi.hip"]
 ARCH = os.environ.get("DPD_OFFLOAD_ARCH", "gfx950")
 
 

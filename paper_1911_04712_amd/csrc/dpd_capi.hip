@@ -107,6 +107,10 @@ struct dpd_box_s {
     bool binned = false;       // pos_b/vel_b/cell_start describe the current state
     bool have_force = false;   // force/pos_b hold the last step's forces
 
+    // pair-force tiling
+    int tile_req[3] = {0, 0, 0};
+    dpd::TileConst tc{};
+
     // captured multi-step graph
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -170,12 +174,36 @@ hipError_t enqueue_bin(dpd_box_s* b, hipStream_t s)
                            b->pos_b, b->vel_b, s);
 }
 
+// Default cell tile of the LDS force kernel (measured on MI355X): 8x4x4
+// cells at solvent densities up to 4.5, 3x3x3 above; both keep two
+// workgroups' LDS per CU.
+void choose_tile(dpd_box_s* b)
+{
+    int t[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
+    if (t[0] <= 0) {
+        const double rho = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
+        const bool dilute = rho <= 4.5;
+        t[0] = dilute ? 8 : 3;
+        t[1] = dilute ? 4 : 3;
+        t[2] = dilute ? 4 : 3;
+    }
+    b->tc = dpd::make_tile_const(b->cells, b->n, t, 0, 0);
+}
+
+hipError_t enqueue_force(dpd_box_s* b, const dpd::ForceConst& fc, hipStream_t s)
+{
+    if (b->params.flags & DPD_FLAG_REFERENCE_FORCE)
+        return dpd::launch_force_gather(b->pos_b, b->vel_b, b->cell_start, b->n, fc, &b->st->step, b->force,
+                                        &b->st->nonfinite, s);
+    return dpd::launch_force_tiled(b->pos_b, b->vel_b, b->cell_start, b->n, fc, b->tc, &b->st->step, b->force,
+                                   &b->st->nonfinite, s);
+}
+
 // Forces on the binned state and the integrate step back into pos_a/vel_a.
 hipError_t enqueue_force_integrate(dpd_box_s* b, hipStream_t s)
 {
     const dpd::ForceConst fc = force_const(b);
-    hipError_t e = dpd::launch_force_gather(b->pos_b, b->vel_b, b->cell_start, b->n, fc, &b->st->step, b->force,
-                                            &b->st->nonfinite, s);
+    hipError_t e = enqueue_force(b, fc, s);
     if (e != hipSuccess) return e;
     if (b->params.flags & DPD_FLAG_VIRIAL) {
         e = dpd::launch_virial(b->pos_b, b->cell_start, b->n, fc, b->st, s);
@@ -280,7 +308,9 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
     b->profile = (long long*)(b->ws + lay.profile);
     b->st = (dpd::DevStats*)(b->ws + lay.stats);
     b->flags = (int*)(b->ws + lay.flags);
-    hipError_t e = dpd::launch_fill_i32(b->count, 0, nc, b->stream);
+    choose_tile(b);
+    hipError_t e = dpd::force_tiled_prepare(b->tc);
+    if (e == hipSuccess) e = dpd::launch_fill_i32(b->count, 0, nc, b->stream);
     if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
     if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
     if (e == hipSuccess) e = dpd::launch_fill_i32(b->flags, 0, 4, b->stream);
@@ -305,12 +335,31 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
         return fail(DPD_EINVAL, "dpd_set_params: flow_axis and grad_axis must be distinct axes in 0..2");
     if (p->profile_bins < 0 || p->profile_bins > dpd::kProfileMaxBins)
         return fail(DPD_EINVAL, "dpd_set_params: profile_bins must be in [0, %d]", dpd::kProfileMaxBins);
-    if (p->flags & ~DPD_FLAG_VIRIAL) return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
+    if (p->flags & ~(DPD_FLAG_VIRIAL | DPD_FLAG_REFERENCE_FORCE)) return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
     const double sig = std::sqrt(2.0 * p->gamma * p->kT) / std::sqrt(p->dt);
     if (!std::isfinite(sig) || sig > 1e8 || std::fabs(p->a) > 1e8 || p->gamma > 1e8)
         return fail(DPD_EINVAL, "dpd_set_params: parameters out of the FP32 force range");
     b->params = *p;
     b->have_params = true;
+    b->graph_dirty = true;
+    return DPD_OK;
+}
+
+int dpd_set_tile(dpd_box b, const int32_t tile[3])
+{
+    if (!b || !tile) return fail(DPD_EINVAL, "dpd_set_tile: null argument");
+    const bool dflt = tile[0] == 0 && tile[1] == 0 && tile[2] == 0;
+    if (!dflt)
+        for (int k = 0; k < 3; ++k)
+            if (tile[k] < 1 || tile[k] > 16) return fail(DPD_EINVAL, "dpd_set_tile: edges must be in 1..16");
+    for (int k = 0; k < 3; ++k) b->tile_req[k] = tile[k];
+    choose_tile(b);
+    if (b->tc.lds_bytes > 160 * 1024) {
+        for (int k = 0; k < 3; ++k) b->tile_req[k] = 0;
+        choose_tile(b);
+        return fail(DPD_EINVAL, "dpd_set_tile: tile needs more LDS than a CU has");
+    }
+    HIPCHK(dpd::force_tiled_prepare(b->tc));
     b->graph_dirty = true;
     return DPD_OK;
 }
@@ -415,9 +464,7 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
         if (e == hipSuccess && !b->binned) e = enqueue_bin(b, b->stream);
         b->binned = false;
         if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
-        if (e == hipSuccess)
-            e = dpd::launch_force_gather(b->pos_b, b->vel_b, b->cell_start, b->n, fc, &b->st->step, b->force,
-                                         &b->st->nonfinite, b->stream);
+        if (e == hipSuccess) e = enqueue_force(b, fc, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
         if (e == hipSuccess && (b->params.flags & DPD_FLAG_VIRIAL))
             e = dpd::launch_virial(b->pos_b, b->cell_start, b->n, fc, b->st, b->stream);

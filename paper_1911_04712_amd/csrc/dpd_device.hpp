@@ -99,4 +99,81 @@ __device__ __forceinline__ float dist2(float dx, float dy, float dz)
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
+// ---- cells and wave/block reductions --------------------------------------
+__device__ __forceinline__ int cell_coord(float x, int L)
+{
+    int c = (int)x;                 // x >= 0 after the wrap: truncation is floor
+    c = c < 0 ? 0 : c;
+    return c > L - 1 ? L - 1 : c;
+}
+
+__device__ __forceinline__ int cell_of(float x, float y, float z, int Lx, int Ly, int Lz)
+{
+    return cell_coord(x, Lx) + Lx * (cell_coord(y, Ly) + Ly * cell_coord(z, Lz));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order (lane tree inside each wave, then waves in
+// index order).  All threads of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch /* >= blockDim/64 */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    T t = T(0);
+    for (int w = 0; w < nw; ++w) t += scratch[w];
+    return t;
+}
+
+// Inclusive scan inside a wave of 64.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan of a[0..n) in place (LDS), a[n] = total; returns the total.
+// scr needs blockDim/64 ints.  All threads of the block must call it.
+__device__ __forceinline__ int block_excl_scan(int* a, int n, int* scr)
+{
+    const int bd = blockDim.x, tid = threadIdx.x;
+    const int per = (n + bd - 1) / bd;
+    const int b0 = tid * per;
+    int sum = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < n) sum += a[b0 + k];
+    const int lane = tid & 63, wave = tid >> 6;
+    const int incl = wave_incl_scan(sum);
+    __syncthreads();
+    if (lane == 63) scr[wave] = incl;
+    __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += scr[w];
+    int run = wpre + incl - sum;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < n) {
+            const int v = a[b0 + k];
+            a[b0 + k] = run;
+            run += v;
+        }
+    if (tid == bd - 1) a[n] = run;
+    __syncthreads();
+    return a[n];
+}
+
 }  // namespace dpd

@@ -63,6 +63,18 @@ struct ForceConst {
     float half_grad;   // L_grad / 2
 };
 
+// Tiling of the box for the LDS pair-force kernel, with the byte offsets of
+// its dynamic LDS buffers.
+struct TileConst {
+    int T[3];          // tile edge in cells (clamped to the box)
+    int ntile[3];      // tiles per axis (the last one may be ragged)
+    int ntiles;
+    int smax;          // staged particles (tile + halo) that fit the LDS buffers
+    int pmax;          // tile particles that fit the accumulators
+    int lds_bytes;
+    int off_sv, off_acc, off_ps, off_cst, off_cg, off_rows, off_q, off_seg;
+};
+
 // Layout of a box inside its caller-provided workspace.  All offsets are
 // 256-byte aligned.
 struct Layout {
@@ -95,6 +107,11 @@ hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* v
 hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n,
                                const ForceConst& fc, const unsigned long long* step, float4* force,
                                int* nonfinite, hipStream_t s);
+TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax_override, int pmax_override);
+hipError_t force_tiled_prepare(const TileConst& tc);
+hipError_t launch_force_tiled(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
+                              const TileConst& tc, const unsigned long long* step, float4* force, int* nonfinite,
+                              hipStream_t s);
 hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const ForceConst& fc,
                          DevStats* st, hipStream_t s);
 hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const float4* force, int n, const StepConst& sc,

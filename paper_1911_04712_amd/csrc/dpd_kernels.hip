@@ -17,54 +17,29 @@
 
 namespace dpd {
 
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int cell_coord(float x, int L)
-{
-    int c = (int)x;                 // x >= 0 after the wrap: truncation is floor
-    c = c < 0 ? 0 : c;
-    return c > L - 1 ? L - 1 : c;
-}
-
-__device__ __forceinline__ int cell_of(float x, float y, float z, int Lx, int Ly, int Lz)
-{
-    return cell_coord(x, Lx) + Lx * (cell_coord(y, Ly) + Ly * cell_coord(z, Lz));
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Block-wide sum in a fixed order (lane tree inside each wave, then waves in
-// index order).  All threads of the block must call it.
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* scratch /* >= blockDim/64 */)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_sum(v);
-    __syncthreads();
-    if (lane == 0) scratch[wave] = v;
-    __syncthreads();
-    T t = T(0);
-    for (int w = 0; w < nw; ++w) t += scratch[w];
-    return t;
-}
-
-// Inclusive scan inside a wave of 64.
-__device__ __forceinline__ int wave_incl_scan(int v)
+// Arrival slot in a per-cell counter, aggregated over runs of equal keys in
+// a wave: lanes l0..l1 holding the same key (consecutive lanes) take one
+// atomicAdd of the run length and slots base + (l - l0).  Particles in cell
+// order mostly stay in their cell, so runs are about rho long.  Lanes with
+// valid == false must pass key = -1.  All lanes of the wave must call it.
+__device__ __forceinline__ int arrival_slot(int key, bool valid, int* __restrict__ count)
 {
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-    }
-    return v;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = valid && (lane == 0 || prev != key);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long live = __ballot(valid);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int my_head = 63 - __clzll(heads & upto);                 // valid lanes only
+    int run_end = 64;
+    const unsigned long long after = heads & ~upto;
+    if (after) run_end = __ffsll((long long)after) - 1;
+    const int nlive = __popcll(live);                               // valid lanes are a prefix
+    if (run_end > nlive) run_end = nlive;
+    int base = 0;
+    if (head) base = atomicAdd(&count[key], run_end - lane);
+    base = __shfl(base, valid ? my_head : lane, 64);
+    return base + (lane - my_head);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,84 +208,6 @@ hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* v
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// pair forces: reference gather form (one thread per particle, all 27 cells)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ pos,
-                                                         const float4* __restrict__ vel,
-                                                         const int* __restrict__ cell_start, int n, ForceConst fc,
-                                                         const unsigned long long* __restrict__ step_ptr,
-                                                         float4* __restrict__ force, int* __restrict__ nonfinite)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t step = (uint32_t)(*step_ptr);
-    const float4 pi = pos[i], vi = vel[i];
-    const uint32_t id_i = __float_as_uint(pi.w);
-    const int Lx = fc.cells[0], Ly = fc.cells[1], Lz = fc.cells[2];
-    const int cx = cell_coord(pi.x, Lx), cy = cell_coord(pi.y, Ly), cz = cell_coord(pi.z, Lz);
-    long long ax = 0, ay = 0, az = 0;
-    bool bad = false;
-    for (int dz = -1; dz <= 1; ++dz) {
-        int nz = cz + dz;
-        float sz = 0.0f;
-        if (nz < 0) { nz += Lz; sz = -fc.L[2]; }
-        else if (nz >= Lz) { nz -= Lz; sz = fc.L[2]; }
-        for (int dy = -1; dy <= 1; ++dy) {
-            int ny = cy + dy;
-            float sy = 0.0f;
-            if (ny < 0) { ny += Ly; sy = -fc.L[1]; }
-            else if (ny >= Ly) { ny -= Ly; sy = fc.L[1]; }
-            for (int dx = -1; dx <= 1; ++dx) {
-                int nx = cx + dx;
-                float sx = 0.0f;
-                if (nx < 0) { nx += Lx; sx = -fc.L[0]; }
-                else if (nx >= Lx) { nx -= Lx; sx = fc.L[0]; }
-                const int cell = nx + Lx * (ny + Ly * nz);
-                const int s = cell_start[cell], e = cell_start[cell + 1];
-                for (int j = s; j < e; ++j) {
-                    if (j == i) continue;
-                    const float4 pj = pos[j];
-                    const float dxx = pi.x - (pj.x + sx);
-                    const float dyy = pi.y - (pj.y + sy);
-                    const float dzz = pi.z - (pj.z + sz);
-                    const float r2 = dist2(dxx, dyy, dzz);
-                    if (!(r2 < 1.0f) || r2 == 0.0f) continue;
-                    const float4 vj = vel[j];
-                    const float xi = pair_xi(id_i, __float_as_uint(pj.w), step, fc.pc.k0, fc.pc.k1);
-                    float rinv;
-                    const float fs = pair_scalar(r2, dxx, dyy, dzz, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, rinv,
-                                                 xi, fc.pc);
-                    const float Fx = fs * (dxx * rinv), Fy = fs * (dyy * rinv), Fz = fs * (dzz * rinv);
-                    if (fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit) {
-                        ax += fx_of(Fx);
-                        ay += fx_of(Fy);
-                        az += fx_of(Fz);
-                    } else {
-                        bad = true;
-                    }
-                }
-            }
-        }
-    }
-    double f[3] = {(double)ax * kFxInv, (double)ay * kFxInv, (double)az * kFxInv};
-    if (fc.body_f != 0.0f) {
-        const float g = fc.grad_axis == 0 ? pi.x : (fc.grad_axis == 1 ? pi.y : pi.z);
-        f[fc.flow_axis] += (double)(g <= fc.half_grad ? -fc.body_f : fc.body_f);
-    }
-    force[i] = make_float4((float)f[0], (float)f[1], (float)f[2], 0.0f);
-    if (bad) atomicOr(nonfinite, 1);
-}
-
-hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
-                               const unsigned long long* step, float4* force, int* nonfinite, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_force_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, cell_start, n,
-                       fc, step, force, nonfinite);
-    return hipGetLastError();
-}
-
 // Conservative virial sum_{i<j} r_ij . F^C_ij = sum_i sum_{j != i} a w r / 2,
 // per particle in FP64, then added as fixed point (order-independent).
 __global__ __launch_bounds__(kBlock) void k_virial(const float4* __restrict__ pos, const int* __restrict__ cell_start,
@@ -379,7 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
     __shared__ long long s_psum[kLdsBins];
     __shared__ int s_pcnt[kLdsBins];
     __shared__ double s_red[kBlock / 64];
-    __shared__ int s_last;
     const bool lds_prof = sc.nbins > 0 && sc.nbins <= kLdsBins;
     if (lds_prof)
         for (int b = threadIdx.x; b < sc.nbins; b += kBlock) { s_psum[b] = 0; s_pcnt[b] = 0; }
@@ -388,8 +284,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
     double m[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false, esc = false;
     const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const float4 x = pos_s[i], v = vel_s[i], f = force[i];
+    for (int i0 = blockIdx.x * kBlock; i0 < n; i0 += stride) {   // uniform per block: all lanes reach arrival_slot
+        const int i = i0 + threadIdx.x;
+        const bool live = i < n;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
+        if (live) {
+            x = pos_s[i];
+            v = vel_s[i];
+            f = force[i];
+        }
         const float vcx = fmaf(f.x, sc.half_dtm, v.x), vcy = fmaf(f.y, sc.half_dtm, v.y),
                     vcz = fmaf(f.z, sc.half_dtm, v.z);
         const float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
@@ -413,8 +316,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
             ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
             nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
         }
-        const int c = cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]);
-        keyslot[i] = make_int2(c, atomicAdd(&count[c], 1));
+        const int c = live ? cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
+        const int slot = arrival_slot(c, live, count);
+        if (!live) continue;
+        keyslot[i] = make_int2(c, slot);
         pos_a[i] = make_float4(nx, ny, nz, x.w);
         vel_a[i] = make_float4(vx, vy, vz, 0.0f);
         if (fin) {
@@ -454,28 +359,36 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
                 atomicAdd((unsigned long long*)&profile[2 * b + 1], (unsigned long long)s_pcnt[b]);
             }
 
-    // The last block to finish folds the per-block partials in block order.
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&st->ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// Fold of the per-block partials of the integrate kernel, in block order
+// (one block; a kernel boundary separates it from the writers).  Also
+// advances the step counter read by the next force evaluation.
+__global__ __launch_bounds__(kBlock) void k_fold_stats(const double* __restrict__ partials, int nblocks, StepConst sc,
+                                                       DevStats* st)
+{
+    __shared__ double s_red[kBlock / 64];
     double tot[kPartials];
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
-            t += __builtin_nontemporal_load(&partials[b * kPartials + k]);
-        tot[k] = block_sum(t, s_red);
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        int b = threadIdx.x;
+        for (; b + 3 * kBlock < nblocks; b += 4 * kBlock) {
+            t0 += partials[b * kPartials + k];
+            t1 += partials[(b + kBlock) * kPartials + k];
+            t2 += partials[(b + 2 * kBlock) * kPartials + k];
+            t3 += partials[(b + 3 * kBlock) * kPartials + k];
+        }
+        for (; b < nblocks; b += kBlock) t0 += partials[b * kPartials + k];
+        tot[k] = block_sum((t0 + t1) + (t2 + t3), s_red);
     }
     if (threadIdx.x == 0) {
         const double mass = sc.mass;
         const double ke_half = 0.5 * mass * tot[3];
         const double ke_c = 0.5 * mass * tot[4];
         const double kT_c = 2.0 * ke_c * sc.inv_dof;
-        const long long vfx = __hip_atomic_exchange(&st->virial_fx, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double vir = (double)vfx / kVirScale;
+        const double vir = (double)st->virial_fx / kVirScale;
+        st->virial_fx = 0;
         const double press = sc.rho * kT_c + vir * sc.inv_vol / 3.0;
         st->last[0] = mass * tot[0];
         st->last[1] = mass * tot[1];
@@ -492,8 +405,6 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
         st->sum_momentum[2] += mass * tot[2];
         st->nsamples += 1;
         st->step += 1;
-        st->ticket = 0;
-        __threadfence();
     }
 }
 
@@ -506,6 +417,7 @@ hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const floa
     if (blocks > kIntegrateMaxBlocks) blocks = kIntegrateMaxBlocks;
     hipLaunchKernelGGL(k_integrate, dim3(blocks), dim3(kBlock), 0, s, pos_s, vel_s, force, n, sc, pos_a, vel_a, count,
                        keyslot, partials, profile, st);
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, s, partials, blocks, sc, st);
     return hipGetLastError();
 }
 

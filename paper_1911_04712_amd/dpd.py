@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, EAGAIN, EBUSY, ENOTFOUND = 0, -
 HOST, DEVICE = 0, 1
 POS, VEL, VEL_CENTRED, FORCE = 0, 1, 2, 3
 FLAG_VIRIAL = 1
+FLAG_REFERENCE_FORCE = 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE",
           EAGAIN: "EAGAIN", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND"}
@@ -64,6 +65,7 @@ SIGNATURES = {
     "dpd_create": ([ctypes.POINTER(Geom), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
     "dpd_set_params": ([_VP, ctypes.POINTER(Params)], ctypes.c_int),
     "dpd_set_seed": ([_VP, ctypes.c_uint64], ctypes.c_int),
+    "dpd_set_tile": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
     "dpd_build_cells": ([_VP], ctypes.c_int),
     "dpd_step": ([_VP, _I64], ctypes.c_int),
@@ -177,6 +179,10 @@ class Box:
         p = params if isinstance(params, Params) else make_params(**(params or {}), **kw)
         _check(lib().dpd_set_params(self._h, ctypes.byref(p)))
         self.params = p
+
+    def set_tile(self, tile):
+        t = (ctypes.c_int32 * 3)(*[int(x) for x in tile])
+        _check(lib().dpd_set_tile(self._h, t))
 
     def set_seed(self, seed):
         _check(lib().dpd_set_seed(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
