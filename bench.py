@@ -41,6 +41,147 @@ def force_ops(n, rho):
     return pairs * OPS_PER_PAIR + cands * OPS_PER_CANDIDATE
 
 
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bench_batched(nboxes=64, steps=500, tune=True):
+    """64 boxes with edges log-uniform in [8, 32], rho = 3, 500 steps: one
+    captured-graph launch for all boxes vs the plain per-box loops."""
+    import numpy as np
+    from paper_1911_04712_amd import dpd, inputs
+    specs = inputs.batch_boxes(nboxes=nboxes, lo=8, hi=32, density=3.0, rng_seed=4)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    states = [inputs.uniform_state(s["cells"], n=s["n"], seed=s["seed"]) for s in specs]
+    boxes = [dpd.Box(s["cells"], s["n"], params=params, seed=s["seed"]) for s in specs]
+    total = sum(s["n"] for s in specs)
+    tiles = {}
+    t_tune = time.perf_counter()
+    if tune:
+        # autotune once per geometry on a scratch box (tiles never change results)
+        for s in specs:
+            key = (tuple(s["cells"]), s["n"])
+            if key in tiles:
+                continue
+            tb = dpd.Box(s["cells"], s["n"], params=params, seed=0)
+            tb.init_random(1.0, 1)
+            tb.step(2)
+            tiles[key] = tb.tune_tile(reps=3)[0]
+            tb.close()
+        for b, s in zip(boxes, specs):
+            b.set_tile(tiles[(tuple(s["cells"]), s["n"])])
+    t_tune = time.perf_counter() - t_tune
+
+    def reset():
+        for b, (p, v) in zip(boxes, states):
+            b.set_state(p, v)
+        _sync()
+
+    # plain loop: box by box, step by step (eager launches)
+    reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for b in boxes:
+            b.step(1)
+    _sync()
+    t_plain = time.perf_counter() - t0
+    ref = boxes[0].read(dpd.POS)
+    # per-box graphs: each box runs its steps through its own captured graph
+    reset()
+    t0 = time.perf_counter()
+    for b in boxes:
+        b.step(steps)
+    _sync()
+    t_boxgraph = time.perf_counter() - t0
+    # batched: one launch of one captured graph for every box and step
+    batch = dpd.Batch(boxes)
+    reset()
+    batch.step(steps)                  # capture + first run
+    _sync()
+    reset()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    _sync()
+    t_batch = time.perf_counter() - t0
+    same = bool(np.array_equal(boxes[0].read(dpd.POS), ref))
+    batch.close()
+    for b in boxes:
+        b.close()
+    ps = total * steps
+    return {"workload": f"{nboxes} boxes, edges log-uniform [8,32], rho=3, {steps} steps", "particles": total,
+            "value": ps / t_batch, "unit": "particle-steps/s",
+            "plain_loop": ps / t_plain, "per_box_graph_loop": ps / t_boxgraph,
+            "speedup_vs_plain": t_plain / t_batch, "speedup_vs_per_box_graph": t_boxgraph / t_batch,
+            "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4), "per_box_graph": round(t_boxgraph, 4),
+                        "autotune": round(t_tune, 3)},
+            "distinct_tiles": sorted({str(t) for t in tiles.values()}), "batched_equals_plain": same}
+
+
+def bench_served(nreq=1000, quantum=50, pool_gb=32, max_slots=256):
+    """Poisson trace of requests (mean 200/s, edges log-uniform [8, 48], rho 3
+    or 8, 500 steps): continuous batching vs FIFO one request at a time."""
+    import numpy as np
+    from paper_1911_04712_amd import dpd, inputs
+    trace = inputs.request_trace(nreq=nreq, rate=200.0, lo=8, hi=48, rng_seed=5, steps=500)
+
+    def params_of(r):
+        return dpd.make_params(a=r["a"], gamma=r["gamma"], kT=r["kT"], dt=r["dt"], body_f=r["body_f"])
+
+    total = sum(r["n"] * r["steps"] for r in trace)
+    # served
+    srv = dpd.Server(int(pool_gb * (1 << 30)), max_slots=max_slots)
+    base = srv.clock()
+    pending = list(trace)
+    live = {}
+    lat = []
+    peak = 0
+    while pending or live:
+        now = srv.clock() - base
+        while pending and pending[0]["t_arrival"] <= now:
+            r = pending.pop(0)
+            t = srv.submit(r["cells"], r["n"], params_of(r), seed=r["seed"], nsteps=r["steps"], init_kT=r["kT"],
+                           init_seed=r["seed"])
+            live[t] = r["t_arrival"]
+        q, a, _ = srv.counts()
+        peak = max(peak, a)
+        if q + a > 0:
+            srv.pump(quantum)
+        elif pending:
+            time.sleep(max(0.0, min(pending[0]["t_arrival"] - now, 0.002)))
+        for t in list(live):
+            res = srv.poll(t)
+            if res is not None:
+                if res[0]["status"] != dpd.OK:
+                    raise RuntimeError(f"request failed: {res[0]}")
+                lat.append(res[0]["t_done"] - base - live.pop(t))
+    makespan = srv.clock() - base
+    srv.close()
+    # FIFO: one request at a time, each stepped alone through its own graph
+    import torch
+    t0 = time.perf_counter()
+    lat_f = []
+    for r in trace:
+        now = time.perf_counter() - t0
+        if r["t_arrival"] > now:
+            time.sleep(r["t_arrival"] - now)
+        b = dpd.Box(r["cells"], r["n"], params=params_of(r), seed=r["seed"])
+        b.init_random(r["kT"], r["seed"])
+        b.step(r["steps"])
+        b.stats()
+        b.close()
+        lat_f.append(time.perf_counter() - t0 - r["t_arrival"])
+    makespan_f = time.perf_counter() - t0
+    lat, lat_f = np.array(lat), np.array(lat_f)
+    return {"workload": f"{nreq} requests, Poisson 200/s, edges log-uniform [8,48], rho 3|8, 500 steps",
+            "value": total / makespan, "unit": "particle-steps/s", "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "makespan_s": makespan, "peak_active": peak,
+            "quantum_steps": quantum,
+            "fifo": {"value": total / makespan_f, "p50_s": float(np.percentile(lat_f, 50)),
+                     "p99_s": float(np.percentile(lat_f, 99)), "makespan_s": makespan_f},
+            "speedup_vs_fifo": makespan_f / makespan}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +191,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage with HIP events")
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -122,6 +268,18 @@ def main():
                                "sample": f"{sample_steps} steps of the same {w.name} box ({n} particles), "
                                          f"{cs:.1f} s"}
     box.close()
+    if not args.no_batched:
+        out["batched"] = bench_batched()
+    if not args.no_served:
+        out["served"] = bench_served(nreq=args.serve_requests)
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
     print(json.dumps(out), flush=True)
 
 

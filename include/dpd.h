@@ -153,6 +153,18 @@ int dpd_set_params(dpd_box box, const dpd_params* params);
  * Results do not depend on the tile shape (bitwise). */
 int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 
+/* The tile shape in use (after clamping to the box). */
+int dpd_get_tile(dpd_box box, int32_t tile[3]);
+
+/* Autotuner: time the LDS pair-force kernel on the box's current positions
+ * for a fixed list of tile shapes (those whose LDS fits a CU), `reps` launches
+ * each with HIP events on the box stream, keep the fastest and report it in
+ * tile_out and *ms_out (mean ms per force evaluation; may be NULL).  The
+ * state does not advance (the box is left holding its cell list, as after
+ * dpd_build_cells) and, since results do not depend on the tile, no result
+ * changes.  Synchronises. */
+int dpd_tune_tile(dpd_box box, int32_t reps, int32_t tile_out[3], double* ms_out);
+
 /* Set the 64-bit seed of the random term. */
 int dpd_set_seed(dpd_box box, uint64_t seed);
 
@@ -162,6 +174,14 @@ int dpd_set_seed(dpd_box box, uint64_t seed);
  * position grid.  vel is taken as v^{-1/2}.  Resets the step counter and
  * the accumulators.  Synchronises the stream. */
 int dpd_set_state(dpd_box box, const float* pos_n3, const float* vel_n3, int where);
+
+/* Load a random state generated on the device: positions uniform on [0, L)
+ * (on the position grid), velocities Maxwellian N(0, kT/m) per component
+ * with the centre-of-mass velocity removed, particle i = id i.  Drawn from
+ * Philox4x32-10 keyed by `seed` on counters disjoint from the pair noise.
+ * Needs params (for m).  Resets the step counter and accumulators.
+ * Synchronises. */
+int dpd_init_random(dpd_box box, double kT, uint64_t seed);
 
 /* Bin the current state into cells without stepping (so dpd_read_raw
  * reports the cell list of the current positions). */
@@ -202,6 +222,92 @@ int dpd_destroy(dpd_box box);
  * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate.  The steps
  * advance the box like dpd_step.  Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
+
+/* ---- batches of independent boxes ------------------------------------------
+ * A batch steps many boxes (uneven sizes, own parameters and seeds) with one
+ * launch per kernel for all of them, and a run of up to 1024 steps is a
+ * single launch of one captured HIP graph.  Each box computes exactly what it
+ * would alone (same work partition, same bits): ids, step counters and seeds
+ * are per box, so no random number depends on the batch. */
+typedef struct dpd_batch_s* dpd_batch;
+
+/* Device bytes of the batch tables (descriptors and work prefixes). */
+int dpd_batch_workspace_bytes(int32_t nboxes, size_t* bytes);
+
+/* Group existing boxes (1..65536, distinct) into a batch working on
+ * `hip_stream` with its tables in `dev_ws` (256-byte aligned, caller-owned,
+ * must outlive the batch).  The boxes stay owned by the caller and must
+ * outlive the batch. */
+int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                     dpd_batch* out);
+
+/* Advance every box by nsteps.  Every box needs params, seed and state and
+ * must not hold a bare cell list (dpd_build_cells / dpd_tune_tile without a
+ * step since).  Picks up each box's current parameters and tile.  Waits for
+ * work pending on the boxes' streams; later work on a box's stream waits for
+ * the batch.  Runs of 64..1024 steps are one launch of a captured graph
+ * (kept for the next call of the same length); shorter runs are launched
+ * directly.  Asynchronous on the batch stream. */
+int dpd_batch_step(dpd_batch batch, int64_t nsteps);
+
+/* Destroy a batch (NULL-safe; the boxes are untouched).  Synchronises. */
+int dpd_batch_destroy(dpd_batch batch);
+
+/* ---- serving ------------------------------------------------------------------
+ * A request server over one caller-owned device pool.  Requests are admitted
+ * in arrival order when a slot is free and their footprint
+ * (dpd_workspace_bytes) fits in the pool; admitted requests keep their state
+ * resident; each pump runs one quantum of steps for all active requests as
+ * one batch, retires finished ones (results copied to host memory, memory
+ * freed) and admits waiting requests, so requests that arrive while others
+ * run join the next quantum.  A request's result is the same bits alone or in
+ * a mix. */
+typedef struct dpd_server_s* dpd_server;
+
+typedef struct {
+    dpd_geom geom;
+    dpd_params params;
+    uint64_t seed;           /* seed of the random term                                  */
+    int64_t nsteps;          /* steps to run (>= 0)                                      */
+    const float* pos_n3;     /* initial state, host, n x 3 (copied at submit); both NULL: */
+    const float* vel_n3;     /*   generated on the device as by dpd_init_random           */
+    double init_kT;          /* temperature of the generated velocities                  */
+    uint64_t init_seed;      /* seed of the generated state                              */
+} dpd_request;
+
+typedef struct {
+    dpd_stats stats;         /* diagnostics at the end of the run                        */
+    int32_t status;          /* DPD_OK, DPD_ENONFINITE or the error that retired it       */
+    int32_t reserved;
+    double t_submit, t_admit, t_done;   /* seconds on the server's steady clock          */
+} dpd_result;
+
+/* Create a server on `dev_pool` (device, 256-byte aligned, caller-owned,
+ * outlives the server) with at most max_slots (1..4096) active requests,
+ * working on `hip_stream`.  A small part of the pool holds the batch tables. */
+int dpd_server_create(void* dev_pool, size_t pool_bytes, int32_t max_slots, void* hip_stream, dpd_server* out);
+
+/* Queue a request (never blocks; DPD_ENOMEM if it could never fit). */
+int dpd_server_submit(dpd_server server, const dpd_request* req, uint64_t* ticket);
+
+/* Admit, run one quantum of up to quantum_steps steps for all active requests
+ * (never past a request's end), retire finished ones, admit again.
+ * *ran_steps (may be NULL) receives the steps run.  Synchronises. */
+int dpd_server_pump(dpd_server server, int32_t quantum_steps, int32_t* ran_steps);
+
+/* DPD_EAGAIN until the request is done; then fills the result and, if not
+ * NULL, the final state (n x 3 floats each, id order) and forgets the ticket
+ * (DPD_ENOTFOUND afterwards). */
+int dpd_server_poll(dpd_server server, uint64_t ticket, dpd_result* res, float* pos_n3, float* vel_n3);
+
+/* Requests waiting, active, and particle-steps completed so far. */
+int dpd_server_counts(dpd_server server, int32_t* queued, int32_t* active, int64_t* particle_steps);
+
+/* Seconds since the server was created (the clock of dpd_result). */
+double dpd_server_clock(dpd_server server);
+
+/* Destroy (NULL-safe): active requests are dropped.  Synchronises. */
+int dpd_server_destroy(dpd_server server);
 
 /* Thread-local message of the last error (never NULL). */
 const char* dpd_last_error(void);

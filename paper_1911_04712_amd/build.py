@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdpd.so")
-SOURCES = ["dpd_kernels.hip", "dpd_force.hip", "dpd_capi.hip"]
+SOURCES = ["dpd_kernels.hip", "dpd_force.hip", "dpd_capi.hip", "dpd_server.cpp"]
 ARCH = os.environ.get("DPD_OFFLOAD_ARCH", "gfx950")
 
 
@@ -29,7 +29,7 @@ def hipcc() -> str:
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC, *extra,

@@ -1,12 +1,24 @@
 // dpd_capi.hip -- host runtime behind include/dpd.h: box state, workspace
-// layout, validation, the step pipeline and its HIP-graph capture.
+// layout, validation, the step pipeline and its HIP-graph capture, batches
+// of boxes and the tile autotuner.
+//
+// Every step kernel reads a per-box descriptor (BoxDesc) from device memory
+// and maps its workgroups to boxes through prefix tables (LaunchPlan), so a
+// box alone is a batch of one and runs the very same kernels, with the same
+// per-box work partition, as inside a batch.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
+#include <vector>
 
 #include "dpd.h"
 #include "dpd_internal.hpp"
+
+static_assert(DPD_FLAG_VIRIAL == dpd::kFlagVirial, "flag mismatch");
+static_assert(DPD_FLAG_REFERENCE_FORCE == dpd::kFlagReference, "flag mismatch");
 
 namespace {
 
@@ -48,9 +60,20 @@ double grid_of(const dpd_geom* g)
     return std::ldexp(1.0, e - 23);
 }
 
+constexpr int kGraphSteps = 8;          // steps per captured graph of a single box
+constexpr int kBatchGraphMax = 1024;    // a batch run of up to this many steps is one graph launch
+constexpr int kBatchGraphMin = 64;      // shorter batch runs are launched directly (no capture)
+constexpr size_t kLdsLimit = 160 * 1024;
+
 }  // namespace
 
 namespace dpd {
+
+int set_error(int code, const char* msg)
+{
+    std::snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
 
 Layout make_layout(int64_t n, int64_t nc)
 {
@@ -73,6 +96,8 @@ Layout make_layout(int64_t n, int64_t nc)
     L.profile = take((size_t)kProfileMaxBins * 2 * sizeof(long long));
     L.stats = take(sizeof(DevStats));
     L.flags = take(4 * sizeof(int));
+    L.desc = take(sizeof(BoxDesc));
+    L.pre = take((size_t)kNumWork * 2 * sizeof(int));
     L.total = off;
     return L;
 }
@@ -89,14 +114,13 @@ struct dpd_box_s {
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     dpd::Layout lay{};
-    float4 *pos_a = nullptr, *vel_a = nullptr, *pos_b = nullptr, *vel_b = nullptr, *force = nullptr;
-    int2* keyslot = nullptr;
-    int* perm = nullptr;
+
+    dpd::BoxDesc hd{};          // host copy of the device descriptor
+    dpd::BoxDesc* d_desc = nullptr;
+    int* d_pre = nullptr;
+    dpd::LaunchPlan lp{};
+    int* flags = nullptr;
     float* out = nullptr;
-    int *count = nullptr, *cell_start = nullptr, *bsum = nullptr, *flags = nullptr;
-    double* partials = nullptr;
-    long long* profile = nullptr;
-    dpd::DevStats* st = nullptr;
 
     dpd_params params{};
     bool have_params = false;
@@ -107,20 +131,28 @@ struct dpd_box_s {
     bool binned = false;       // pos_b/vel_b/cell_start describe the current state
     bool have_force = false;   // force/pos_b hold the last step's forces
 
-    // pair-force tiling
     int tile_req[3] = {0, 0, 0};
-    dpd::TileConst tc{};
 
     // captured multi-step graph
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
-    int graph_steps = 0;
     bool graph_dirty = true;
 };
 
-namespace {
+struct dpd_batch_s {
+    std::vector<dpd_box_s*> boxes;
+    hipStream_t stream = nullptr;
+    dpd::BoxDesc* d_desc = nullptr;
+    int* d_pre = nullptr;
+    std::vector<int> pre;      // host copy [kNumWork][nbox + 1]
+    dpd::LaunchPlan lp{};
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int64_t graph_steps = 0;
+    hipEvent_t done = nullptr;
+};
 
-constexpr int kGraphSteps = 8;
+namespace {
 
 dpd::ForceConst force_const(const dpd_box_s* b)
 {
@@ -167,19 +199,11 @@ dpd::StepConst step_const(const dpd_box_s* b)
     return sc;
 }
 
-// Binning of pos_a into pos_b/vel_b + cell_start (keys must be valid).
-hipError_t enqueue_bin(dpd_box_s* b, hipStream_t s)
-{
-    return dpd::launch_bin(b->keyslot, b->pos_a, b->vel_a, b->n, b->nc, b->count, b->bsum, b->cell_start, b->perm,
-                           b->pos_b, b->vel_b, s);
-}
-
 // Default cell tile of the LDS force kernel (measured on MI355X): 8x4x4
-// cells at solvent densities up to 4.5, 3x3x3 above; both keep two
-// workgroups' LDS per CU.
-void choose_tile(dpd_box_s* b)
+// cells at solvent densities up to 4.5, 3x3x3 above.
+dpd::TileConst tile_for(const dpd_box_s* b, const int* req)
 {
-    int t[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
+    int t[3] = {req[0], req[1], req[2]};
     if (t[0] <= 0) {
         const double rho = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
         const bool dilute = rho <= 4.5;
@@ -187,57 +211,95 @@ void choose_tile(dpd_box_s* b)
         t[1] = dilute ? 4 : 3;
         t[2] = dilute ? 4 : 3;
     }
-    b->tc = dpd::make_tile_const(b->cells, b->n, t, 0, 0);
+    return dpd::make_tile_const(b->cells, b->n, t, 0, 0);
 }
 
-hipError_t enqueue_force(dpd_box_s* b, const dpd::ForceConst& fc, hipStream_t s)
+// Rebuild the host descriptor and single-box plan from the box's current
+// settings and copy both to the device (stream-ordered, then synchronised so
+// the host buffers can change again).
+int push_desc(dpd_box_s* b)
 {
-    if (b->params.flags & DPD_FLAG_REFERENCE_FORCE)
-        return dpd::launch_force_gather(b->pos_b, b->vel_b, b->cell_start, b->n, fc, &b->st->step, b->force,
-                                        &b->st->nonfinite, s);
-    return dpd::launch_force_tiled(b->pos_b, b->vel_b, b->cell_start, b->n, fc, b->tc, &b->st->step, b->force,
-                                   &b->st->nonfinite, s);
-}
-
-// Forces on the binned state and the integrate step back into pos_a/vel_a.
-hipError_t enqueue_force_integrate(dpd_box_s* b, hipStream_t s)
-{
-    const dpd::ForceConst fc = force_const(b);
-    hipError_t e = enqueue_force(b, fc, s);
-    if (e != hipSuccess) return e;
-    if (b->params.flags & DPD_FLAG_VIRIAL) {
-        e = dpd::launch_virial(b->pos_b, b->cell_start, b->n, fc, b->st, s);
-        if (e != hipSuccess) return e;
+    dpd::BoxDesc& d = b->hd;
+    char* w = b->ws;
+    const dpd::Layout& L = b->lay;
+    d.pos_a = (float4*)(w + L.pos_a);
+    d.vel_a = (float4*)(w + L.vel_a);
+    d.pos_b = (float4*)(w + L.pos_b);
+    d.vel_b = (float4*)(w + L.vel_b);
+    d.force = (float4*)(w + L.force);
+    d.keyslot = (int2*)(w + L.keyslot);
+    d.perm = (int*)(w + L.perm);
+    d.count = (int*)(w + L.count);
+    d.cell_start = (int*)(w + L.cell_start);
+    d.bsum = (int*)(w + L.bsum);
+    d.partials = (double*)(w + L.partials);
+    d.profile = (long long*)(w + L.profile);
+    d.st = (dpd::DevStats*)(w + L.stats);
+    d.n = b->n;
+    d.nc = b->nc;
+    d.nchunks = (b->nc + dpd::kScanChunk - 1) / dpd::kScanChunk;
+    d.nblk_int = dpd::integrate_blocks(b->n);
+    d.flags = b->have_params ? b->params.flags : 0;
+    if (b->have_params) {
+        d.fc = force_const(b);
+        d.sc = step_const(b);
     }
-    const dpd::StepConst sc = step_const(b);
-    return dpd::launch_integrate(b->pos_b, b->vel_b, b->force, b->n, sc, b->pos_a, b->vel_a, b->count, b->keyslot,
-                                 b->partials, b->profile, b->st, s);
+    d.tc = tile_for(b, b->tile_req);
+    int pre[dpd::kNumWork * 2];
+    for (int k = 0; k < dpd::kNumWork; ++k) {
+        pre[2 * k] = 0;
+        pre[2 * k + 1] = dpd::box_work(d, k);
+        b->lp.total[k] = pre[2 * k + 1];
+    }
+    b->lp.desc = b->d_desc;
+    b->lp.pre = b->d_pre;
+    b->lp.nbox = 1;
+    b->lp.lds_force = d.tc.lds_bytes;
+    b->lp.any_virial = (d.flags & DPD_FLAG_VIRIAL) != 0;
+    b->lp.reference_force = (d.flags & DPD_FLAG_REFERENCE_FORCE) != 0;
+    HIPCHK(dpd::force_tiled_prepare(d.tc.lds_bytes));
+    HIPCHK(hipMemcpyAsync(b->d_desc, &d, sizeof d, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_pre, pre, sizeof pre, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return DPD_OK;
 }
 
-int rebuild_graph(dpd_box_s* b)
+hipError_t enqueue_step_tail(const dpd::LaunchPlan& lp, hipStream_t s)
 {
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = dpd::launch_force(lp, s);
+    if (e == hipSuccess) e = dpd::launch_virial(lp, s);
+    if (e == hipSuccess) e = dpd::launch_integrate(lp, s);
+    return e;
+}
+
+hipError_t enqueue_steps(const dpd::LaunchPlan& lp, int64_t nsteps, hipStream_t s)
+{
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = enqueue_bin(b, b->cap_stream);
-        if (e == hipSuccess) e = enqueue_force_integrate(b, b->cap_stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        e = dpd::launch_bin(lp, s);
+        if (e == hipSuccess) e = enqueue_step_tail(lp, s);
     }
-    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+    return e;
+}
+
+int capture(const dpd::LaunchPlan& lp, int64_t nsteps, hipStream_t* cap, hipGraphExec_t* exec)
+{
+    if (*exec) {
+        (void)hipGraphExecDestroy(*exec);
+        *exec = nullptr;
+    }
+    if (!*cap) HIPCHK(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(*cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_steps(lp, nsteps, *cap);
+    hipError_t e2 = hipStreamEndCapture(*cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return fail(DPD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(DPD_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    b->graph_steps = kGraphSteps;
-    b->graph_dirty = false;
     return DPD_OK;
 }
 
@@ -248,6 +310,8 @@ int sync_box(dpd_box_s* b)
 }
 
 hipMemcpyKind kind_to(int where) { return where == DPD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+bool ready(const dpd_box_s* b) { return b->have_params && b->have_seed && b->have_state; }
 
 }  // namespace
 
@@ -293,31 +357,24 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
     b->stream = (hipStream_t)hip_stream;
     b->ws = (char*)dev_ws;
     b->lay = lay;
-    b->pos_a = (float4*)(b->ws + lay.pos_a);
-    b->vel_a = (float4*)(b->ws + lay.vel_a);
-    b->pos_b = (float4*)(b->ws + lay.pos_b);
-    b->vel_b = (float4*)(b->ws + lay.vel_b);
-    b->force = (float4*)(b->ws + lay.force);
-    b->keyslot = (int2*)(b->ws + lay.keyslot);
-    b->perm = (int*)(b->ws + lay.perm);
-    b->out = (float*)(b->ws + lay.out);
-    b->count = (int*)(b->ws + lay.count);
-    b->cell_start = (int*)(b->ws + lay.cell_start);
-    b->bsum = (int*)(b->ws + lay.bsum);
-    b->partials = (double*)(b->ws + lay.partials);
-    b->profile = (long long*)(b->ws + lay.profile);
-    b->st = (dpd::DevStats*)(b->ws + lay.stats);
+    b->d_desc = (dpd::BoxDesc*)(b->ws + lay.desc);
+    b->d_pre = (int*)(b->ws + lay.pre);
     b->flags = (int*)(b->ws + lay.flags);
-    choose_tile(b);
-    hipError_t e = dpd::force_tiled_prepare(b->tc);
-    if (e == hipSuccess) e = dpd::launch_fill_i32(b->count, 0, nc, b->stream);
-    if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
-    if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
-    if (e == hipSuccess) e = dpd::launch_fill_i32(b->flags, 0, 4, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
+    b->out = (float*)(b->ws + lay.out);
+    int rc = push_desc(b);
+    hipError_t e = hipSuccess;
+    if (rc == DPD_OK) {
+        e = dpd::launch_fill_i32(b->hd.count, 0, nc, b->stream);
+        if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->hd.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
+        if (e == hipSuccess)
+            e = dpd::launch_fill_i32((int*)b->hd.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
+        if (e == hipSuccess) e = dpd::launch_fill_i32(b->flags, 0, 4, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) rc = fail(DPD_EDEVICE, "dpd_create: %s", hipGetErrorString(e));
+    }
+    if (rc != DPD_OK) {
         delete b;
-        return fail(DPD_EDEVICE, "dpd_create: %s", hipGetErrorString(e));
+        return rc;
     }
     *out = b;
     return DPD_OK;
@@ -339,10 +396,11 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
     const double sig = std::sqrt(2.0 * p->gamma * p->kT) / std::sqrt(p->dt);
     if (!std::isfinite(sig) || sig > 1e8 || std::fabs(p->a) > 1e8 || p->gamma > 1e8)
         return fail(DPD_EINVAL, "dpd_set_params: parameters out of the FP32 force range");
+    const int old_flags = b->have_params ? b->params.flags : -1;
     b->params = *p;
     b->have_params = true;
-    b->graph_dirty = true;
-    return DPD_OK;
+    if (old_flags != p->flags) b->graph_dirty = true;   // the launch sequence depends on the flags only
+    return push_desc(b);
 }
 
 int dpd_set_tile(dpd_box b, const int32_t tile[3])
@@ -352,15 +410,17 @@ int dpd_set_tile(dpd_box b, const int32_t tile[3])
     if (!dflt)
         for (int k = 0; k < 3; ++k)
             if (tile[k] < 1 || tile[k] > 16) return fail(DPD_EINVAL, "dpd_set_tile: edges must be in 1..16");
-    for (int k = 0; k < 3; ++k) b->tile_req[k] = tile[k];
-    choose_tile(b);
-    if (b->tc.lds_bytes > 160 * 1024) {
-        for (int k = 0; k < 3; ++k) b->tile_req[k] = 0;
-        choose_tile(b);
+    if ((size_t)tile_for(b, tile).lds_bytes > kLdsLimit)
         return fail(DPD_EINVAL, "dpd_set_tile: tile needs more LDS than a CU has");
-    }
-    HIPCHK(dpd::force_tiled_prepare(b->tc));
+    for (int k = 0; k < 3; ++k) b->tile_req[k] = tile[k];
     b->graph_dirty = true;
+    return push_desc(b);
+}
+
+int dpd_get_tile(dpd_box b, int32_t tile[3])
+{
+    if (!b || !tile) return fail(DPD_EINVAL, "dpd_get_tile: null argument");
+    for (int k = 0; k < 3; ++k) tile[k] = b->hd.tc.T[k];
     return DPD_OK;
 }
 
@@ -369,8 +429,7 @@ int dpd_set_seed(dpd_box b, uint64_t seed)
     if (!b) return fail(DPD_EINVAL, "dpd_set_seed: null box");
     b->seed = seed;
     b->have_seed = true;
-    b->graph_dirty = true;
-    return DPD_OK;
+    return push_desc(b);
 }
 
 int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where)
@@ -379,25 +438,48 @@ int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where
     if (where != DPD_HOST && where != DPD_DEVICE) return fail(DPD_EINVAL, "dpd_set_state: bad `where`");
     if (b->n > 0 && (!pos_n3 || !vel_n3)) return fail(DPD_EINVAL, "dpd_set_state: null array");
     b->have_state = b->keys_valid = b->binned = b->have_force = false;
+    const dpd::BoxDesc& d = b->hd;
     const float *pp = pos_n3, *vp = vel_n3;
     const size_t bytes = (size_t)b->n * 3 * sizeof(float);
     if (where == DPD_HOST && b->n > 0) {
-        HIPCHK(hipMemcpyAsync(b->pos_b, pos_n3, bytes, hipMemcpyHostToDevice, b->stream));
-        HIPCHK(hipMemcpyAsync(b->vel_b, vel_n3, bytes, hipMemcpyHostToDevice, b->stream));
-        pp = (const float*)b->pos_b;
-        vp = (const float*)b->vel_b;
+        HIPCHK(hipMemcpyAsync(d.pos_b, pos_n3, bytes, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(d.vel_b, vel_n3, bytes, hipMemcpyHostToDevice, b->stream));
+        pp = (const float*)d.pos_b;
+        vp = (const float*)d.vel_b;
     }
     HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
-    HIPCHK(dpd::launch_fill_i32(b->count, 0, b->nc, b->stream));
-    HIPCHK(dpd::launch_fill_i32((int*)b->st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream));
-    HIPCHK(dpd::launch_fill_i32((int*)b->profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream));
-    HIPCHK(dpd::launch_load_state(pp, vp, b->n, b->pos_a, b->vel_a, (float)b->q, (float)(1.0 / b->q), b->L, b->flags,
+    HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
+    HIPCHK(dpd::launch_fill_i32((int*)d.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream));
+    HIPCHK(dpd::launch_fill_i32((int*)d.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream));
+    HIPCHK(dpd::launch_load_state(pp, vp, b->n, d.pos_a, d.vel_a, (float)b->q, (float)(1.0 / b->q), b->L, b->flags,
                                   b->stream));
-    HIPCHK(dpd::launch_keys(b->pos_a, b->n, b->cells, b->count, b->keyslot, b->stream));
+    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, b->flags, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     if (bad) return fail(DPD_EINVAL, "dpd_set_state: a position is outside [0, L) or a value is non-finite");
+    b->have_state = true;
+    b->keys_valid = true;
+    return DPD_OK;
+}
+
+int dpd_init_random(dpd_box b, double kT, uint64_t seed)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_init_random: null box");
+    if (!b->have_params) return fail(DPD_ESTATE, "dpd_init_random: set params first (the mass scales velocities)");
+    if (!std::isfinite(kT) || kT < 0.0) return fail(DPD_EINVAL, "dpd_init_random: kT must be finite and >= 0");
+    b->have_state = b->keys_valid = b->binned = b->have_force = false;
+    const dpd::BoxDesc& d = b->hd;
+    HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
+    HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
+    HIPCHK(dpd::launch_fill_i32((int*)d.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream));
+    HIPCHK(dpd::launch_fill_i32((int*)d.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream));
+    // the id-order staging buffer (12 B per particle) holds the per-block sums
+    const int scratch = (int)std::min<int64_t>((int64_t)b->n * 3 / 2, (int64_t)1 << 30);
+    HIPCHK(dpd::launch_init_random(b->n, b->L, (float)b->q, std::sqrt(kT / b->params.mass), seed, d.pos_a, d.vel_a,
+                                   (double*)b->out, scratch, b->stream));
+    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
     b->have_state = true;
     b->keys_valid = true;
     return DPD_OK;
@@ -408,7 +490,7 @@ int dpd_build_cells(dpd_box b)
     if (!b) return fail(DPD_EINVAL, "dpd_build_cells: null box");
     if (!b->have_state) return fail(DPD_ESTATE, "dpd_build_cells: no state loaded");
     if (b->binned) return DPD_OK;
-    HIPCHK(enqueue_bin(b, b->stream));
+    HIPCHK(dpd::launch_bin(b->lp, b->stream));
     b->binned = true;
     b->keys_valid = false;
     b->have_force = false;
@@ -419,29 +501,23 @@ int dpd_step(dpd_box b, int64_t nsteps)
 {
     if (!b) return fail(DPD_EINVAL, "dpd_step: null box");
     if (nsteps < 0) return fail(DPD_EINVAL, "dpd_step: nsteps < 0");
-    if (!b->have_params || !b->have_seed || !b->have_state)
-        return fail(DPD_ESTATE, "dpd_step: set params, seed and state first");
+    if (!ready(b)) return fail(DPD_ESTATE, "dpd_step: set params, seed and state first");
     if (nsteps == 0) return DPD_OK;
     int64_t left = nsteps;
     if (b->binned) {                      // first step reuses the existing cell list
-        HIPCHK(enqueue_force_integrate(b, b->stream));
+        HIPCHK(enqueue_step_tail(b->lp, b->stream));
         b->binned = false;
         --left;
     }
     if (left >= kGraphSteps) {
         if (b->graph_dirty || !b->graph) {
-            const int rc = rebuild_graph(b);
+            const int rc = capture(b->lp, kGraphSteps, &b->cap_stream, &b->graph);
             if (rc) return rc;
+            b->graph_dirty = false;
         }
-        while (left >= b->graph_steps) {
-            HIPCHK(hipGraphLaunch(b->graph, b->stream));
-            left -= b->graph_steps;
-        }
+        for (; left >= kGraphSteps; left -= kGraphSteps) HIPCHK(hipGraphLaunch(b->graph, b->stream));
     }
-    for (; left > 0; --left) {
-        HIPCHK(enqueue_bin(b, b->stream));
-        HIPCHK(enqueue_force_integrate(b, b->stream));
-    }
+    HIPCHK(enqueue_steps(b->lp, left, b->stream));
     b->keys_valid = true;
     b->have_force = true;
     return DPD_OK;
@@ -451,27 +527,21 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
 {
     if (!b || !ms_out) return fail(DPD_EINVAL, "dpd_profile_steps: null argument");
     if (nsteps < 1) return fail(DPD_EINVAL, "dpd_profile_steps: nsteps < 1");
-    if (!b->have_params || !b->have_seed || !b->have_state)
-        return fail(DPD_ESTATE, "dpd_profile_steps: set params, seed and state first");
+    if (!ready(b)) return fail(DPD_ESTATE, "dpd_profile_steps: set params, seed and state first");
     hipEvent_t ev[5] = {};
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     double acc[4] = {0, 0, 0, 0};
     int rc = DPD_OK;
     for (int64_t k = 0; k < nsteps && rc == DPD_OK; ++k) {
-        const dpd::ForceConst fc = force_const(b);
-        const dpd::StepConst sc = step_const(b);
         hipError_t e = hipEventRecord(ev[0], b->stream);
-        if (e == hipSuccess && !b->binned) e = enqueue_bin(b, b->stream);
+        if (e == hipSuccess && !b->binned) e = dpd::launch_bin(b->lp, b->stream);
         b->binned = false;
         if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
-        if (e == hipSuccess) e = enqueue_force(b, fc, b->stream);
+        if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
-        if (e == hipSuccess && (b->params.flags & DPD_FLAG_VIRIAL))
-            e = dpd::launch_virial(b->pos_b, b->cell_start, b->n, fc, b->st, b->stream);
+        if (e == hipSuccess) e = dpd::launch_virial(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
-        if (e == hipSuccess)
-            e = dpd::launch_integrate(b->pos_b, b->vel_b, b->force, b->n, sc, b->pos_a, b->vel_a, b->count,
-                                      b->keyslot, b->partials, b->profile, b->st, b->stream);
+        if (e == hipSuccess) e = dpd::launch_integrate(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4], b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
         for (int s = 0; s < 4 && e == hipSuccess; ++s) {
@@ -489,27 +559,86 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
     return DPD_OK;
 }
 
+int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
+{
+    if (!b || !tile_out) return fail(DPD_EINVAL, "dpd_tune_tile: null argument");
+    if (reps < 1 || reps > 1000) return fail(DPD_EINVAL, "dpd_tune_tile: reps must be in 1..1000");
+    if (!ready(b)) return fail(DPD_ESTATE, "dpd_tune_tile: set params, seed and state first");
+    if (b->params.flags & DPD_FLAG_REFERENCE_FORCE)
+        return fail(DPD_EINVAL, "dpd_tune_tile: the reference force path has no tiles");
+    // The force kernel is timed on the current positions (binned once); the
+    // state does not advance and the results do not depend on the tile.
+    if (!b->binned) {
+        HIPCHK(dpd::launch_bin(b->lp, b->stream));
+        b->binned = true;
+        b->keys_valid = false;
+    }
+    static const int cand[][3] = {{8, 4, 4}, {4, 4, 4}, {4, 4, 8}, {8, 8, 4}, {6, 4, 4}, {4, 4, 2}, {3, 3, 3},
+                                  {4, 2, 2}, {6, 6, 4}, {2, 2, 2}, {8, 2, 2}, {4, 4, 6}};
+    const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bt[3] = {0, 0, 0};
+    int rc = DPD_OK;
+    for (const auto& c : cand) {
+        if ((size_t)tile_for(b, c).lds_bytes > kLdsLimit) continue;
+        for (int k = 0; k < 3; ++k) b->tile_req[k] = c[k];
+        rc = push_desc(b);
+        if (rc) break;
+        float ms = 0.0f;
+        hipError_t e = dpd::launch_force(b->lp, b->stream);          // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(DPD_EDEVICE, "dpd_tune_tile: %s", hipGetErrorString(e));
+            break;
+        }
+        const double per = ms / reps;
+        if (per < best) {
+            best = per;
+            for (int k = 0; k < 3; ++k) bt[k] = b->hd.tc.T[k];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int k = 0; k < 3; ++k) b->tile_req[k] = rc == DPD_OK && bt[0] > 0 ? bt[k] : saved[k];
+    b->have_force = false;
+    b->graph_dirty = true;
+    const int rc2 = push_desc(b);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    for (int k = 0; k < 3; ++k) tile_out[k] = bt[k];
+    if (ms_out) *ms_out = best;
+    return DPD_OK;
+}
+
 int dpd_read(dpd_box b, int what, float* out_n3, int where)
 {
     if (!b) return fail(DPD_EINVAL, "dpd_read: null box");
     if (where != DPD_HOST && where != DPD_DEVICE) return fail(DPD_EINVAL, "dpd_read: bad `where`");
     if (b->n > 0 && !out_n3) return fail(DPD_EINVAL, "dpd_read: null output");
     if (!b->have_state) return fail(DPD_ESTATE, "dpd_read: no state loaded");
+    const dpd::BoxDesc& d = b->hd;
     float* dst = where == DPD_DEVICE ? out_n3 : b->out;
     switch (what) {
     case DPD_POS:
-        HIPCHK(dpd::launch_to_rows(b->pos_a, nullptr, 0.0f, b->pos_a, b->n, dst, b->stream));
+        HIPCHK(dpd::launch_to_rows(d.pos_a, nullptr, 0.0f, d.pos_a, b->n, dst, b->stream));
         break;
     case DPD_VEL:
-        HIPCHK(dpd::launch_to_rows(b->vel_a, nullptr, 0.0f, b->pos_a, b->n, dst, b->stream));
+        HIPCHK(dpd::launch_to_rows(d.vel_a, nullptr, 0.0f, d.pos_a, b->n, dst, b->stream));
         break;
     case DPD_FORCE:
         if (!b->have_force) return fail(DPD_ESTATE, "dpd_read: no forces (step first)");
-        HIPCHK(dpd::launch_to_rows(b->force, nullptr, 0.0f, b->pos_b, b->n, dst, b->stream));
+        HIPCHK(dpd::launch_to_rows(d.force, nullptr, 0.0f, d.pos_b, b->n, dst, b->stream));
         break;
     case DPD_VEL_CENTRED:
         if (!b->have_force) return fail(DPD_ESTATE, "dpd_read: no forces (step first)");
-        HIPCHK(dpd::launch_to_rows(b->vel_a, b->force, (float)(-0.5 * b->params.dt / b->params.mass), b->pos_b, b->n,
+        HIPCHK(dpd::launch_to_rows(d.vel_a, d.force, (float)(-0.5 * b->params.dt / b->params.mass), d.pos_b, b->n,
                                    dst, b->stream));
         break;
     default:
@@ -525,11 +654,12 @@ int dpd_read_raw(dpd_box b, float* pos4, float* vel4, int32_t* cell_start, int w
     if (!b) return fail(DPD_EINVAL, "dpd_read_raw: null box");
     if (where != DPD_HOST && where != DPD_DEVICE) return fail(DPD_EINVAL, "dpd_read_raw: bad `where`");
     if (!(b->binned || b->have_force)) return fail(DPD_ESTATE, "dpd_read_raw: no cell list (build_cells or step first)");
+    const dpd::BoxDesc& d = b->hd;
     const size_t pb = (size_t)b->n * sizeof(float4);
-    if (pos4 && b->n > 0) HIPCHK(hipMemcpyAsync(pos4, b->pos_b, pb, kind_to(where), b->stream));
-    if (vel4 && b->n > 0) HIPCHK(hipMemcpyAsync(vel4, b->vel_b, pb, kind_to(where), b->stream));
+    if (pos4 && b->n > 0) HIPCHK(hipMemcpyAsync(pos4, d.pos_b, pb, kind_to(where), b->stream));
+    if (vel4 && b->n > 0) HIPCHK(hipMemcpyAsync(vel4, d.vel_b, pb, kind_to(where), b->stream));
     if (cell_start)
-        HIPCHK(hipMemcpyAsync(cell_start, b->cell_start, (size_t)(b->nc + 1) * sizeof(int), kind_to(where), b->stream));
+        HIPCHK(hipMemcpyAsync(cell_start, d.cell_start, (size_t)(b->nc + 1) * sizeof(int), kind_to(where), b->stream));
     return sync_box(b);
 }
 
@@ -537,7 +667,7 @@ int dpd_get_stats(dpd_box b, dpd_stats* out)
 {
     if (!b || !out) return fail(DPD_EINVAL, "dpd_get_stats: null argument");
     dpd::DevStats s;
-    HIPCHK(hipMemcpyAsync(&s, b->st, sizeof s, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(&s, b->hd.st, sizeof s, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     std::memset(out, 0, sizeof *out);
     for (int k = 0; k < 3; ++k) {
@@ -564,8 +694,9 @@ int dpd_get_profile(dpd_box b, double* sum_v, double* count, int32_t nbins)
     if (!b || !sum_v || !count) return fail(DPD_EINVAL, "dpd_get_profile: null argument");
     if (!b->have_params || nbins != b->params.profile_bins || nbins <= 0)
         return fail(DPD_EINVAL, "dpd_get_profile: nbins must equal params.profile_bins (> 0)");
-    static thread_local long long buf[2 * dpd::kProfileMaxBins];
-    HIPCHK(hipMemcpyAsync(buf, b->profile, (size_t)nbins * 2 * sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+    std::vector<long long> buf((size_t)nbins * 2);
+    HIPCHK(hipMemcpyAsync(buf.data(), b->hd.profile, (size_t)nbins * 2 * sizeof(long long), hipMemcpyDeviceToHost,
+                          b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     for (int k = 0; k < nbins; ++k) {
         sum_v[k] = (double)buf[2 * k] / dpd::kProfScale;
@@ -577,11 +708,11 @@ int dpd_get_profile(dpd_box b, double* sum_v, double* count, int32_t nbins)
 int dpd_reset_accumulators(dpd_box b)
 {
     if (!b) return fail(DPD_EINVAL, "dpd_reset_accumulators: null box");
-    char* base = (char*)b->st;
+    char* base = (char*)b->hd.st;
     const size_t off = offsetof(dpd::DevStats, sum_kT_centred);
     const size_t len = offsetof(dpd::DevStats, nsamples) + sizeof(unsigned long long) - off;
     HIPCHK(hipMemsetAsync(base + off, 0, len, b->stream));
-    HIPCHK(hipMemsetAsync(b->profile, 0, (size_t)dpd::kProfileMaxBins * 2 * sizeof(long long), b->stream));
+    HIPCHK(hipMemsetAsync(b->hd.profile, 0, (size_t)dpd::kProfileMaxBins * 2 * sizeof(long long), b->stream));
     return DPD_OK;
 }
 
@@ -595,6 +726,145 @@ int dpd_destroy(dpd_box b)
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_destroy: %s", hipGetErrorString(e));
     return DPD_OK;
 }
+
+// ---- batches ------------------------------------------------------------------
+
+int dpd_batch_workspace_bytes(int32_t nboxes, size_t* bytes)
+{
+    if (nboxes < 1 || nboxes > 65536 || !bytes) return fail(DPD_EINVAL, "dpd_batch_workspace_bytes: bad arguments");
+    *bytes = align256((size_t)nboxes * sizeof(dpd::BoxDesc)) + align256((size_t)dpd::kNumWork * (nboxes + 1) * sizeof(int));
+    return DPD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Copy the member boxes' descriptors into the batch table and rebuild the
+// prefix tables (boxes' parameters may have changed since creation).
+int batch_refresh(dpd_batch_s* bt)
+{
+    const int nb = (int)bt->boxes.size();
+    std::vector<dpd::BoxDesc> h(nb);
+    bt->pre.assign((size_t)dpd::kNumWork * (nb + 1), 0);
+    int lds = 0;
+    bool virial = false;
+    for (int i = 0; i < nb; ++i) {
+        h[i] = bt->boxes[i]->hd;
+        lds = std::max(lds, h[i].tc.lds_bytes);
+        virial |= (h[i].flags & DPD_FLAG_VIRIAL) != 0;
+        for (int k = 0; k < dpd::kNumWork; ++k)
+            bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
+    }
+    bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial;
+    for (int k = 0; k < dpd::kNumWork; ++k) {
+        const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
+        changed |= bt->lp.total[k] != tot;
+        bt->lp.total[k] = tot;
+    }
+    bt->lp.desc = bt->d_desc;
+    bt->lp.pre = bt->d_pre;
+    bt->lp.nbox = nb;
+    bt->lp.lds_force = lds;
+    bt->lp.any_virial = virial;
+    bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
+    if (changed) bt->graph_steps = 0;   // launch shape changed: capture again
+    HIPCHK(dpd::force_tiled_prepare(lds));
+    HIPCHK(hipMemcpyAsync(bt->d_desc, h.data(), (size_t)nb * sizeof(dpd::BoxDesc), hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(hipMemcpyAsync(bt->d_pre, bt->pre.data(), bt->pre.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                     dpd_batch* out)
+{
+    if (!out) return fail(DPD_EINVAL, "dpd_batch_create: null output");
+    *out = nullptr;
+    size_t need = 0;
+    const int rc0 = dpd_batch_workspace_bytes(nboxes, &need);
+    if (rc0) return rc0;
+    if (!boxes) return fail(DPD_EINVAL, "dpd_batch_create: null box list");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(DPD_EINVAL, "dpd_batch_create: workspace null or misaligned");
+    if (ws_bytes < need) return fail(DPD_ENOMEM, "dpd_batch_create: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    for (int i = 0; i < nboxes; ++i) {
+        if (!boxes[i]) return fail(DPD_EINVAL, "dpd_batch_create: null box %d", i);
+        for (int j = 0; j < i; ++j)
+            if (boxes[j] == boxes[i]) return fail(DPD_EINVAL, "dpd_batch_create: box %d listed twice", i);
+    }
+    dpd_batch_s* bt = new (std::nothrow) dpd_batch_s();
+    if (!bt) return fail(DPD_ENOMEM, "dpd_batch_create: host allocation failed");
+    bt->boxes.assign(boxes, boxes + nboxes);
+    bt->stream = (hipStream_t)hip_stream;
+    bt->d_desc = (dpd::BoxDesc*)dev_ws;
+    bt->d_pre = (int*)((char*)dev_ws + align256((size_t)nboxes * sizeof(dpd::BoxDesc)));
+    bt->lp.lds_force = -1;
+    hipError_t e = hipEventCreateWithFlags(&bt->done, hipEventDisableTiming);
+    int rc = e == hipSuccess ? batch_refresh(bt) : fail(DPD_EDEVICE, "dpd_batch_create: %s", hipGetErrorString(e));
+    if (rc) {
+        if (bt->done) (void)hipEventDestroy(bt->done);
+        delete bt;
+        return rc;
+    }
+    *out = bt;
+    return DPD_OK;
+}
+
+int dpd_batch_step(dpd_batch bt, int64_t nsteps)
+{
+    if (!bt) return fail(DPD_EINVAL, "dpd_batch_step: null batch");
+    if (nsteps < 0) return fail(DPD_EINVAL, "dpd_batch_step: nsteps < 0");
+    for (size_t i = 0; i < bt->boxes.size(); ++i) {
+        dpd_box_s* b = bt->boxes[i];
+        if (!ready(b)) return fail(DPD_ESTATE, "dpd_batch_step: box %zu lacks params, seed or state", i);
+        if (b->binned) return fail(DPD_ESTATE, "dpd_batch_step: box %zu holds a bare cell list; step it once alone", i);
+    }
+    if (nsteps == 0) return DPD_OK;
+    for (dpd_box_s* b : bt->boxes) HIPCHK(hipStreamSynchronize(b->stream));
+    int rc = batch_refresh(bt);
+    if (rc) return rc;
+    // One graph holds the whole run (up to kBatchGraphMax steps), so a run is
+    // a single launch; longer runs replay it.  Short runs (a serving quantum
+    // on a changing set of boxes) are launched directly.
+    int64_t left = nsteps;
+    if (nsteps >= kBatchGraphMin) {
+        const int64_t g = nsteps < kBatchGraphMax ? nsteps : kBatchGraphMax;
+        if (bt->graph_steps != g) {
+            rc = capture(bt->lp, g, &bt->cap_stream, &bt->graph);
+            if (rc) return rc;
+            bt->graph_steps = g;
+        }
+        for (; left >= g; left -= g) HIPCHK(hipGraphLaunch(bt->graph, bt->stream));
+    }
+    HIPCHK(enqueue_steps(bt->lp, left, bt->stream));
+    // later work on each box's own stream waits for the batch
+    HIPCHK(hipEventRecord(bt->done, bt->stream));
+    for (dpd_box_s* b : bt->boxes) {
+        HIPCHK(hipStreamWaitEvent(b->stream, bt->done, 0));
+        b->keys_valid = true;
+        b->have_force = true;
+        b->binned = false;
+    }
+    return DPD_OK;
+}
+
+int dpd_batch_destroy(dpd_batch bt)
+{
+    if (!bt) return DPD_OK;
+    hipError_t e = hipStreamSynchronize(bt->stream);
+    if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+    if (bt->done) (void)hipEventDestroy(bt->done);
+    delete bt;
+    if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_batch_destroy: %s", hipGetErrorString(e));
+    return DPD_OK;
+}
+
+// ---- random-term diagnostics -----------------------------------------------
 
 int dpd_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, int where, void* hip_stream)
 {

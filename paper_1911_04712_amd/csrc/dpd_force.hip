@@ -110,26 +110,17 @@ __device__ float4 gather_force_one(int i, const float4* __restrict__ pos, const 
     return finish_force(ax, ay, az, pi, fc);
 }
 
-__global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ pos,
-                                                         const float4* __restrict__ vel,
-                                                         const int* __restrict__ cell_start, int n, ForceConst fc,
-                                                         const unsigned long long* __restrict__ step_ptr,
-                                                         float4* __restrict__ force, int* __restrict__ nonfinite)
+__global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restrict__ desc,
+                                                         const int* __restrict__ pre, int nbox)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int* __restrict__ pre_ = pre + kWPart * (nbox + 1);
+    const int box = nbox == 1 ? 0 : find_box(pre_, nbox, (int)blockIdx.x);
+    const BoxDesc& d = desc[box];
+    const int i = ((int)blockIdx.x - pre_[box]) * kBlock + threadIdx.x;
+    if (i >= d.n) return;
     bool bad = false;
-    force[i] = gather_force_one(i, pos, vel, cell_start, fc, (uint32_t)(*step_ptr), bad);
-    if (bad) atomicOr(nonfinite, 1);
-}
-
-hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
-                               const unsigned long long* step, float4* force, int* nonfinite, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_force_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, cell_start, n,
-                       fc, step, force, nonfinite);
-    return hipGetLastError();
+    d.force[i] = gather_force_one(i, d.pos_b, d.vel_b, d.cell_start, d.fc, (uint32_t)d.st->step, bad);
+    if (bad) atomicOr(&d.st->nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -156,11 +147,19 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_force_tiled(const float4* __restrict__ pos, const float4* __restrict__ vel,
-                                                        const int* __restrict__ cell_start, ForceConst fc,
-                                                        TileConst tc, const unsigned long long* __restrict__ step_ptr,
-                                                        float4* __restrict__ force, int* __restrict__ nonfinite)
+__global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                        int nbox)
 {
+    const int* __restrict__ pre_ = pre + kWTile * (nbox + 1);
+    const int box = nbox == 1 ? 0 : find_box(pre_, nbox, (int)blockIdx.x);
+    const BoxDesc& d = desc[box];
+    const ForceConst& fc = d.fc;
+    const TileConst& tc = d.tc;
+    const float4* __restrict__ pos = d.pos_b;
+    const float4* __restrict__ vel = d.vel_b;
+    const int* __restrict__ cell_start = d.cell_start;
+    float4* __restrict__ force = d.force;
+    int* __restrict__ nonfinite = &d.st->nonfinite;
     extern __shared__ __align__(16) unsigned char lds[];
     float4* sp = (float4*)lds;                                  // staged positions (image-shifted), w = id
     float4* sv = (float4*)(lds + tc.off_sv);                    // staged velocities, w = tile index or -1
@@ -174,9 +173,11 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const float4* __restrict
     __shared__ int s_scr[kBlock / 64];
 
     // Consecutive tiles go to the same XCD (workgroups are dealt to the 8
-    // XCDs round-robin), so neighbouring tiles share halo cells in one L2.
-    const int per_xcd = gridDim.x >> 3;
-    const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    // XCDs round-robin and every box's range starts at a multiple of 8), so
+    // neighbouring tiles share halo cells in one L2.
+    const int lb = (int)blockIdx.x - pre_[box];
+    const int per_xcd = (pre_[box + 1] - pre_[box]) >> 3;
+    const int t = (lb & 7) * per_xcd + (lb >> 3);
     if (t >= tc.ntiles) return;
     const int L0 = fc.cells[0], L1 = fc.cells[1], L2 = fc.cells[2];
     const int tx = t % tc.ntile[0], ty = (t / tc.ntile[0]) % tc.ntile[1], tz = t / (tc.ntile[0] * tc.ntile[1]);
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const float4* __restrict
     const int S0 = P0 + 2, S1 = P1 + 2, S2 = P2 + 2;
     const int ncs = S0 * S1 * S2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const uint32_t step = (uint32_t)(*step_ptr);
+    const uint32_t step = (uint32_t)d.st->step;
 
     // 1. HBM start and particle count of every staged cell (the only
     //    dependent HBM round trip before the copy), scanned into LDS offsets
@@ -222,8 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const float4* __restrict
     __syncthreads();
     const int nt = s_scr[0];
 
-    if (S > tc.smax || nt > tc.pmax) {
-        // Overfull tile: gather from HBM, same arithmetic and same bits.
+    if (S > tc.smax || nt > tc.pmax || (d.flags & kFlagReference)) {
+        // Overfull tile (or the box asks for the reference path): gather
+        // from HBM, same arithmetic and same bits.
         bool bad = false;
         for (int r = wave; r < nrows; r += nw) {
             const int4 rw = rows[r];
@@ -434,21 +436,22 @@ TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax
     return tc;
 }
 
-hipError_t launch_force_tiled(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
-                              const TileConst& tc, const unsigned long long* step, float4* force, int* nonfinite,
-                              hipStream_t s)
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    const int blocks = ((tc.ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL(k_force_tiled, dim3(blocks), dim3(kBlock), tc.lds_bytes, s, pos, vel, cell_start, fc, tc, step,
-                       force, nonfinite);
+    if (lp.reference_force) {
+        if (lp.total[kWPart] > 0)
+            hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    } else if (lp.total[kWTile] > 0) {
+        hipLaunchKernelGGL(k_force_tiled, dim3(lp.total[kWTile]), dim3(kBlock), lp.lds_force, s, lp.desc, lp.pre,
+                           lp.nbox);
+    }
     return hipGetLastError();
 }
 
-hipError_t force_tiled_prepare(const TileConst& tc)
+hipError_t force_tiled_prepare(int lds_bytes)
 {
-    if (tc.lds_bytes > 65536)
-        return hipFuncSetAttribute((const void*)k_force_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, tc.lds_bytes);
+    if (lds_bytes > 65536)
+        return hipFuncSetAttribute((const void*)k_force_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     return hipSuccess;
 }
 

@@ -13,6 +13,8 @@ constexpr int kScanChunk = 2048;        // cells per block of the cell-count sca
 constexpr int kIntegrateMaxBlocks = 2048;
 constexpr int kProfileMaxBins = 4096;
 constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred
+constexpr int kFlagVirial = 1;          // DPD_FLAG_VIRIAL
+constexpr int kFlagReference = 2;       // DPD_FLAG_REFERENCE_FORCE
 
 // Fixed-point scale of the flow-profile and virial accumulators.
 constexpr double kProfScale = 16777216.0;      // 2^24 units per velocity unit
@@ -75,6 +77,45 @@ struct TileConst {
     int off_sv, off_acc, off_ps, off_cst, off_cg, off_rows, off_q, off_seg;
 };
 
+// Everything a kernel needs about one box, in device memory.  The step
+// kernels read it at run time, so parameters can change between launches
+// of a captured graph.  A single box is a batch of one.
+struct BoxDesc {
+    float4 *pos_a, *vel_a;     // state in the previous cell order (or id order)
+    float4 *pos_b, *vel_b;     // state binned into cell order
+    float4* force;             // total force of the last step, cell order
+    int2* keyslot;             // (cell, arrival slot) of pos_a
+    int* perm;                 // cell order -> index into pos_a (arrival order)
+    int* count;                // particles per cell (zeroed by the scan)
+    int* cell_start;           // nc + 1
+    int* bsum;                 // chunk sums of count
+    double* partials;          // integrate per-block partials (kPartials each)
+    long long* profile;        // flow profile accumulators (sum, count) per slab
+    DevStats* st;
+    int n, nc, nchunks;
+    int nblk_int;              // integrate blocks of this box (depends on n only)
+    int flags;                 // DPD_FLAG_* of the box
+    int pad0;
+    ForceConst fc;
+    StepConst sc;
+    TileConst tc;
+};
+
+// Work decomposition of one launch group (a box, or a batch of boxes): per
+// kernel kind, the exclusive prefix over boxes of the workgroups each box
+// needs; a workgroup finds its box by binary search.
+enum WorkKind { kWChunk = 0, kWPart = 1, kWTile = 2, kWInt = 3, kNumWork = 4 };
+
+struct LaunchPlan {
+    const BoxDesc* desc;       // device array [nbox]
+    const int* pre;            // device array [kNumWork][nbox + 1]
+    int nbox;
+    int total[kNumWork];       // workgroups per kind
+    int lds_force;             // dynamic LDS of the tile kernel (max over boxes)
+    bool any_virial;
+    bool reference_force;      // single box flagged DPD_FLAG_REFERENCE_FORCE
+};
+
 // Layout of a box inside its caller-provided workspace.  All offsets are
 // 256-byte aligned.
 struct Layout {
@@ -91,35 +132,43 @@ struct Layout {
     size_t profile;           // long long[kProfileMaxBins * 2] (sum, count)
     size_t stats;             // DevStats
     size_t flags;             // int[4] scratch flags
+    size_t desc;              // BoxDesc
+    size_t pre;               // int[kNumWork * 2] launch prefixes of the box alone
     size_t total;
 };
 
 Layout make_layout(int64_t n, int64_t nc);
+int set_error(int code, const char* msg);   // thread-local message behind dpd_last_error
+int integrate_blocks(int n);
+int box_work(const BoxDesc& d, int kind);
 
-// ---- kernel launchers (dpd_kernels.hip) -----------------------------------
+// ---- kernel launchers ------------------------------------------------------
 hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s);
 hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4* pos, float4* vel,
                              float q, float inv_q, const float* L, int* bad, hipStream_t s);
+hipError_t launch_init_random(int n, const float* L, float q, double vscale, uint64_t seed, float4* pos, float4* vel,
+                              double* scratch, int scratch_doubles, hipStream_t s);
 hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s);
-hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* vel_in, int n, int nc,
-                      int* count, int* bsum, int* cell_start, int* perm, float4* pos_out, float4* vel_out,
-                      hipStream_t s);
-hipError_t launch_force_gather(const float4* pos, const float4* vel, const int* cell_start, int n,
-                               const ForceConst& fc, const unsigned long long* step, float4* force,
-                               int* nonfinite, hipStream_t s);
+hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s);
+hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
+hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
 TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax_override, int pmax_override);
-hipError_t force_tiled_prepare(const TileConst& tc);
-hipError_t launch_force_tiled(const float4* pos, const float4* vel, const int* cell_start, int n, const ForceConst& fc,
-                              const TileConst& tc, const unsigned long long* step, float4* force, int* nonfinite,
-                              hipStream_t s);
-hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const ForceConst& fc,
-                         DevStats* st, hipStream_t s);
-hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const float4* force, int n, const StepConst& sc,
-                            float4* pos_a, float4* vel_a, int* count, int2* keyslot, double* partials,
-                            long long* profile, DevStats* st, hipStream_t s);
+hipError_t force_tiled_prepare(int lds_bytes);
 hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,
                           float* out3, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, hipStream_t s);
 hipError_t launch_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi, hipStream_t s);
+
+// Box of workgroup `b` of a launch group (exclusive prefix pre[0..nbox]).
+__device__ __forceinline__ int find_box(const int* __restrict__ pre, int nbox, int b)
+{
+    int lo = 0, hi = nbox;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 }  // namespace dpd

@@ -96,6 +96,79 @@ hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4
     return hipGetLastError();
 }
 
+// Random initial state on the device: positions uniform on [0, L) on the
+// grid q, velocities N(0, kT/m) per component (Box-Muller), from Philox with
+// counters (i, 0xffffffff, k, 1) -- the last word keeps these streams apart
+// from the pair-noise counters, whose last word is 0.  Per-block FP64 sums
+// of the velocities go to `partials` for the centre-of-mass removal.
+__global__ __launch_bounds__(kBlock) void k_init_random(int n, float Lx, float Ly, float Lz, float q, float inv_q,
+                                                        float vscale, uint32_t k0, uint32_t k1,
+                                                        float4* __restrict__ pos, float4* __restrict__ vel,
+                                                        double* __restrict__ partials)
+{
+    __shared__ double s_red[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double sv[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+        const uint4 a = philox10(make_uint4((uint32_t)i, 0xffffffffu, 0u, 1u), k0, k1);
+        const uint4 b = philox10(make_uint4((uint32_t)i, 0xffffffffu, 1u, 1u), k0, k1);
+        const uint4 c = philox10(make_uint4((uint32_t)i, 0xffffffffu, 2u, 1u), k0, k1);
+        const float L[3] = {Lx, Ly, Lz};
+        const uint32_t w[3] = {a.x, a.y, a.z};
+        float x[3];
+        for (int k = 0; k < 3; ++k) {
+            const float u = (float)(w[k] >> 8) * 0x1p-24f;                 // [0, 1)
+            float v = floorf(u * L[k] * inv_q) * q;
+            x[k] = v >= L[k] ? 0.0f : v;
+        }
+        const float g0 = box_muller(b.x, b.y), g1 = box_muller(b.z, b.w), g2 = box_muller(c.x, c.y);
+        const float v3[3] = {g0 * vscale, g1 * vscale, g2 * vscale};
+        pos[i] = make_float4(x[0], x[1], x[2], __int_as_float(i));
+        vel[i] = make_float4(v3[0], v3[1], v3[2], 0.0f);
+        for (int k = 0; k < 3; ++k) sv[k] = (double)v3[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        const double t = block_sum(sv[k], s_red);
+        if (threadIdx.x == 0) partials[blockIdx.x * 3 + k] = t;
+    }
+}
+
+// Mean velocity from the per-block sums (fixed order), subtracted from every
+// particle (FP32).
+__global__ __launch_bounds__(kBlock) void k_remove_com(int n, int nblocks, const double* __restrict__ partials,
+                                                       float4* __restrict__ vel)
+{
+    __shared__ double s_mean[3];
+    __shared__ double s_red[kBlock / 64];
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[b * 3 + k];
+        t = block_sum(t, s_red);
+        if (threadIdx.x == 0) s_mean[k] = n > 0 ? t / (double)n : 0.0;
+    }
+    __syncthreads();
+    const float mx = (float)s_mean[0], my = (float)s_mean[1], mz = (float)s_mean[2];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        float4 v = vel[i];
+        v.x -= mx;
+        v.y -= my;
+        v.z -= mz;
+        vel[i] = v;
+    }
+}
+
+hipError_t launch_init_random(int n, const float* L, float q, double vscale, uint64_t seed, float4* pos, float4* vel,
+                              double* scratch, int scratch_doubles, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (n + kBlock - 1) / kBlock;
+    if (blocks * 3 > scratch_doubles) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_init_random, dim3(blocks), dim3(kBlock), 0, s, n, L[0], L[1], L[2], q, 1.0f / q,
+                       (float)vscale, (uint32_t)seed, (uint32_t)(seed >> 32), pos, vel, scratch);
+    hipLaunchKernelGGL(k_remove_com, dim3(blocks < 1024 ? blocks : 1024), dim3(kBlock), 0, s, n, blocks, scratch, vel);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
@@ -117,32 +190,63 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(const int* __restrict__ count, int nc, int* __restrict__ bsum)
+// ---------------------------------------------------------------------------
+// step kernels: each workgroup finds its box in the launch group, then works
+// on that box exactly as it would alone (same partition, same order)
+// ---------------------------------------------------------------------------
+#define DPD_BOX_OF(kind)                                                       \
+    const int* __restrict__ pre_ = pre + (kind) * (nbox + 1);                  \
+    const int box_ = nbox == 1 ? 0 : find_box(pre_, nbox, (int)blockIdx.x);   \
+    const BoxDesc& d = desc[box_];                                             \
+    const int lb = (int)blockIdx.x - pre_[box_];
+
+int integrate_blocks(int n)
 {
+    int b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return b > kIntegrateMaxBlocks ? kIntegrateMaxBlocks : b;
+}
+
+int box_work(const BoxDesc& d, int kind)
+{
+    switch (kind) {
+    case kWChunk: return d.nchunks;
+    case kWPart: return (d.n + kBlock - 1) / kBlock;
+    case kWTile: return ((d.tc.ntiles + 7) / 8) * 8;       // padded for the XCD swizzle
+    default: return d.nblk_int;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                       int nbox)
+{
+    DPD_BOX_OF(kWChunk)
     __shared__ int scratch[kBlock / 64];
-    const int base = blockIdx.x * kScanChunk;
+    const int base = lb * kScanChunk;
     int v = 0;
 #pragma unroll
     for (int k = 0; k < kScanChunk / kBlock; ++k) {
         const int c = base + k * kBlock + threadIdx.x;
-        if (c < nc) v += count[c];
+        if (c < d.nc) v += d.count[c];
     }
     v = block_sum(v, scratch);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+    if (threadIdx.x == 0) d.bsum[lb] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan(int* __restrict__ count, int nc, const int* __restrict__ bsum,
-                                                 int n, int* __restrict__ cell_start)
+__global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ desc, const int* __restrict__ pre, int nbox)
 {
+    DPD_BOX_OF(kWChunk)
     constexpr int per = kScanChunk / kBlock;   // 8 consecutive cells per thread
     __shared__ int scratch[kBlock / 64];
     __shared__ int wtot[kBlock / 64];
+    const int nc = d.nc;
+    int* __restrict__ count = d.count;
     // prefix of this chunk: sum of the chunk sums before it
-    int pre = 0;
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) pre += bsum[k];
-    pre = block_sum(pre, scratch);
+    int prefix = 0;
+    for (int k = threadIdx.x; k < lb; k += kBlock) prefix += d.bsum[k];
+    prefix = block_sum(prefix, scratch);
 
-    const int c0 = blockIdx.x * kScanChunk + threadIdx.x * per;
+    const int c0 = lb * kScanChunk + threadIdx.x * per;
     int v[per];
     int tsum = 0;
 #pragma unroll
@@ -156,67 +260,71 @@ __global__ __launch_bounds__(kBlock) void k_scan(int* __restrict__ count, int nc
     __syncthreads();
     int wpre = 0;
     for (int w = 0; w < wave; ++w) wpre += wtot[w];
-    int run = pre + wpre + incl - tsum;
+    int run = prefix + wpre + incl - tsum;
 #pragma unroll
     for (int k = 0; k < per; ++k) {
         if (c0 + k < nc) {
-            cell_start[c0 + k] = run;
+            d.cell_start[c0 + k] = run;
             count[c0 + k] = 0;
         }
         run += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell_start[nc] = n;
+    if (lb == d.nchunks - 1 && threadIdx.x == 0) d.cell_start[nc] = d.n;
 }
 
-__global__ void k_scatter(const int2* __restrict__ keyslot, const int* __restrict__ cell_start, int n,
-                          int* __restrict__ perm)
+__global__ __launch_bounds__(kBlock) void k_scatter(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                    int nbox)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int2 ks = keyslot[i];
-    perm[cell_start[ks.x] + ks.y] = i;
+    DPD_BOX_OF(kWPart)
+    const int i = lb * kBlock + threadIdx.x;
+    if (i >= d.n) return;
+    const int2 ks = d.keyslot[i];
+    d.perm[d.cell_start[ks.x] + ks.y] = i;
 }
 
-__global__ void k_gather(const int* __restrict__ perm, const int2* __restrict__ keyslot,
-                         const int* __restrict__ cell_start, const float4* __restrict__ pos_in,
-                         const float4* __restrict__ vel_in, int n, float4* __restrict__ pos_out,
-                         float4* __restrict__ vel_out)
+__global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                   int nbox)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    DPD_BOX_OF(kWPart)
+    const int p = lb * kBlock + threadIdx.x;
+    if (p >= d.n) return;
+    const int* __restrict__ perm = d.perm;
     const int i = perm[p];
-    const int c = keyslot[i].x;
-    const int s = cell_start[c], e = cell_start[c + 1];
+    const int c = d.keyslot[i].x;
+    const int s = d.cell_start[c], e = d.cell_start[c + 1];
     int rank = 0;
     for (int t = s; t < e; ++t) rank += perm[t] < i;
-    pos_out[s + rank] = pos_in[i];
-    vel_out[s + rank] = vel_in[i];
+    d.pos_b[s + rank] = d.pos_a[i];
+    d.vel_b[s + rank] = d.vel_a[i];
 }
 
-hipError_t launch_bin(const int2* keyslot, const float4* pos_in, const float4* vel_in, int n, int nc, int* count,
-                      int* bsum, int* cell_start, int* perm, float4* pos_out, float4* vel_out, hipStream_t s)
+hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s)
 {
-    const int nchunks = (nc + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_chunk_sums, dim3(nchunks), dim3(kBlock), 0, s, count, nc, bsum);
-    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(kBlock), 0, s, count, nc, bsum, n, cell_start);
-    if (n > 0) {
-        const dim3 g((n + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_scatter, g, dim3(kBlock), 0, s, keyslot, cell_start, n, perm);
-        hipLaunchKernelGGL(k_gather, g, dim3(kBlock), 0, s, perm, keyslot, cell_start, pos_in, vel_in, n,
-                           pos_out, vel_out);
+    if (lp.total[kWChunk] > 0) {
+        hipLaunchKernelGGL(k_chunk_sums, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+        hipLaunchKernelGGL(k_scan, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    }
+    if (lp.total[kWPart] > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+        hipLaunchKernelGGL(k_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     }
     return hipGetLastError();
 }
 
 // Conservative virial sum_{i<j} r_ij . F^C_ij = sum_i sum_{j != i} a w r / 2,
 // per particle in FP64, then added as fixed point (order-independent).
-__global__ __launch_bounds__(kBlock) void k_virial(const float4* __restrict__ pos, const int* __restrict__ cell_start,
-                                                   int n, ForceConst fc, DevStats* st)
+__global__ __launch_bounds__(kBlock) void k_virial(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                   int nbox)
 {
+    DPD_BOX_OF(kWPart)
+    if (!(d.flags & kFlagVirial)) return;
     __shared__ long long scratch[kBlock / 64];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const ForceConst& fc = d.fc;
+    const float4* __restrict__ pos = d.pos_b;
+    const int* __restrict__ cell_start = d.cell_start;
+    const int i = lb * kBlock + threadIdx.x;
     double acc = 0.0;
-    if (i < n) {
+    if (i < d.n) {
         const float4 pi = pos[i];
         const int Lx = fc.cells[0], Ly = fc.cells[1], Lz = fc.cells[2];
         const int cx = cell_coord(pi.x, Lx), cy = cell_coord(pi.y, Ly), cz = cell_coord(pi.z, Lz);
@@ -250,14 +358,13 @@ __global__ __launch_bounds__(kBlock) void k_virial(const float4* __restrict__ po
     }
     long long v = (long long)llrint(acc * kVirScale);
     v = block_sum(v, scratch);
-    if (threadIdx.x == 0 && v != 0) atomicAdd((unsigned long long*)&st->virial_fx, (unsigned long long)v);
+    if (threadIdx.x == 0 && v != 0) atomicAdd((unsigned long long*)&d.st->virial_fx, (unsigned long long)v);
 }
 
-hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const ForceConst& fc, DevStats* st,
-                         hipStream_t s)
+hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_virial, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, cell_start, n, fc, st);
+    if (!lp.any_virial || lp.total[kWPart] <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_virial, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     return hipGetLastError();
 }
 
@@ -266,25 +373,32 @@ hipError_t launch_virial(const float4* pos, const int* cell_start, int n, const 
 // ---------------------------------------------------------------------------
 constexpr int kLdsBins = 1024;
 
-__global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__ pos_s, const float4* __restrict__ vel_s,
-                                                      const float4* __restrict__ force, int n, StepConst sc,
-                                                      float4* __restrict__ pos_a, float4* __restrict__ vel_a,
-                                                      int* __restrict__ count, int2* __restrict__ keyslot,
-                                                      double* __restrict__ partials, long long* __restrict__ profile,
-                                                      DevStats* st)
+__global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
+                                                      int nbox)
 {
+    DPD_BOX_OF(kWInt)
     __shared__ long long s_psum[kLdsBins];
     __shared__ int s_pcnt[kLdsBins];
     __shared__ double s_red[kBlock / 64];
-    const bool lds_prof = sc.nbins > 0 && sc.nbins <= kLdsBins;
+    const StepConst& sc = d.sc;
+    const int n = d.n;
+    const float4* __restrict__ pos_s = d.pos_b;
+    const float4* __restrict__ vel_s = d.vel_b;
+    const float4* __restrict__ force = d.force;
+    float4* __restrict__ pos_a = d.pos_a;
+    float4* __restrict__ vel_a = d.vel_a;
+    int2* __restrict__ keyslot = d.keyslot;
+    long long* __restrict__ profile = d.profile;
+    const int nbins = sc.nbins;
+    const bool lds_prof = nbins > 0 && nbins <= kLdsBins;
     if (lds_prof)
-        for (int b = threadIdx.x; b < sc.nbins; b += kBlock) { s_psum[b] = 0; s_pcnt[b] = 0; }
+        for (int b = threadIdx.x; b < nbins; b += kBlock) { s_psum[b] = 0; s_pcnt[b] = 0; }
     __syncthreads();
 
     double m[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false, esc = false;
-    const int stride = gridDim.x * kBlock;
-    for (int i0 = blockIdx.x * kBlock; i0 < n; i0 += stride) {   // uniform per block: all lanes reach arrival_slot
+    const int stride = d.nblk_int * kBlock;
+    for (int i0 = lb * kBlock; i0 < n; i0 += stride) {   // uniform per block: all lanes reach arrival_slot
         const int i = i0 + threadIdx.x;
         const bool live = i < n;
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
@@ -317,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
             nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
         }
         const int c = live ? cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
-        const int slot = arrival_slot(c, live, count);
+        const int slot = arrival_slot(c, live, d.count);
         if (!live) continue;
         keyslot[i] = make_int2(c, slot);
         pos_a[i] = make_float4(nx, ny, nz, x.w);
@@ -328,10 +442,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
             m[2] += (double)vz;
             m[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
             m[4] += (double)vcx * vcx + (double)vcy * vcy + (double)vcz * vcz;
-            if (sc.nbins > 0) {
+            if (nbins > 0) {
                 const float g = sc.grad_axis == 0 ? x.x : (sc.grad_axis == 1 ? x.y : x.z);
                 int b = (int)(g * sc.grad_scale);
-                b = b < 0 ? 0 : (b > sc.nbins - 1 ? sc.nbins - 1 : b);
+                b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
                 const float vflow = sc.flow_axis == 0 ? vcx : (sc.flow_axis == 1 ? vcy : vcz);
                 const long long q = llrint((double)vflow * kProfScale);
                 if (lds_prof) {
@@ -344,30 +458,33 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const float4* __restrict__
             }
         }
     }
-    if (bad) atomicOr(&st->nonfinite, 1);
-    if (esc) atomicOr(&st->escaped, 1);
+    if (bad) atomicOr(&d.st->nonfinite, 1);
+    if (esc) atomicOr(&d.st->escaped, 1);
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
         const double t = block_sum(m[k], s_red);
-        if (threadIdx.x == 0) partials[blockIdx.x * kPartials + k] = t;
+        if (threadIdx.x == 0) d.partials[lb * kPartials + k] = t;
     }
     __syncthreads();
     if (lds_prof)
-        for (int b = threadIdx.x; b < sc.nbins; b += kBlock)
+        for (int b = threadIdx.x; b < nbins; b += kBlock)
             if (s_pcnt[b]) {
                 atomicAdd((unsigned long long*)&profile[2 * b], (unsigned long long)s_psum[b]);
                 atomicAdd((unsigned long long*)&profile[2 * b + 1], (unsigned long long)s_pcnt[b]);
             }
-
 }
 
-// Fold of the per-block partials of the integrate kernel, in block order
-// (one block; a kernel boundary separates it from the writers).  Also
-// advances the step counter read by the next force evaluation.
-__global__ __launch_bounds__(kBlock) void k_fold_stats(const double* __restrict__ partials, int nblocks, StepConst sc,
-                                                       DevStats* st)
+// Fold of a box's integrate partials, in block order (one workgroup per box;
+// a kernel boundary separates it from the writers).  Also advances the step
+// counter read by the next force evaluation.
+__global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict__ desc)
 {
+    const BoxDesc& d = desc[blockIdx.x];
     __shared__ double s_red[kBlock / 64];
+    const double* __restrict__ partials = d.partials;
+    const int nblocks = d.nblk_int;
+    const StepConst& sc = d.sc;
+    DevStats* st = d.st;
     double tot[kPartials];
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
@@ -408,16 +525,10 @@ __global__ __launch_bounds__(kBlock) void k_fold_stats(const double* __restrict_
     }
 }
 
-hipError_t launch_integrate(const float4* pos_s, const float4* vel_s, const float4* force, int n, const StepConst& sc,
-                            float4* pos_a, float4* vel_a, int* count, int2* keyslot, double* partials,
-                            long long* profile, DevStats* st, hipStream_t s)
+hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s)
 {
-    int blocks = (n + kBlock - 1) / kBlock;
-    if (blocks < 1) blocks = 1;
-    if (blocks > kIntegrateMaxBlocks) blocks = kIntegrateMaxBlocks;
-    hipLaunchKernelGGL(k_integrate, dim3(blocks), dim3(kBlock), 0, s, pos_s, vel_s, force, n, sc, pos_a, vel_a, count,
-                       keyslot, partials, profile, st);
-    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, s, partials, blocks, sc, st);
+    hipLaunchKernelGGL(k_integrate, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    hipLaunchKernelGGL(k_fold_stats, dim3(lp.nbox), dim3(kBlock), 0, s, lp.desc);
     return hipGetLastError();
 }
 

@@ -57,6 +57,17 @@ class Stats(ctypes.Structure):
                 "step": int(self.step), "nonfinite": int(self.nonfinite), "escaped": int(self.escaped)}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("params", Params), ("seed", ctypes.c_uint64), ("nsteps", ctypes.c_int64),
+                ("pos_n3", ctypes.c_void_p), ("vel_n3", ctypes.c_void_p), ("init_kT", ctypes.c_double),
+                ("init_seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("stats", Stats), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 # Every symbol include/dpd.h declares, with its ctypes signature.
 _VP, _I64 = ctypes.c_void_p, ctypes.c_int64
 SIGNATURES = {
@@ -66,6 +77,23 @@ SIGNATURES = {
     "dpd_set_params": ([_VP, ctypes.POINTER(Params)], ctypes.c_int),
     "dpd_set_seed": ([_VP, ctypes.c_uint64], ctypes.c_int),
     "dpd_set_tile": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "dpd_get_tile": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "dpd_tune_tile": ([_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+                      ctypes.c_int),
+    "dpd_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "dpd_batch_create": ([ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)],
+                         ctypes.c_int),
+    "dpd_batch_step": ([_VP, _I64], ctypes.c_int),
+    "dpd_batch_destroy": ([_VP], ctypes.c_int),
+    "dpd_init_random": ([_VP, ctypes.c_double, ctypes.c_uint64], ctypes.c_int),
+    "dpd_server_create": ([_VP, ctypes.c_size_t, ctypes.c_int32, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "dpd_server_submit": ([_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "dpd_server_pump": ([_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "dpd_server_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(Result), _VP, _VP], ctypes.c_int),
+    "dpd_server_counts": ([_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "dpd_server_clock": ([_VP], ctypes.c_double),
+    "dpd_server_destroy": ([_VP], ctypes.c_int),
     "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
     "dpd_build_cells": ([_VP], ctypes.c_int),
     "dpd_step": ([_VP, _I64], ctypes.c_int),
@@ -184,6 +212,19 @@ class Box:
         t = (ctypes.c_int32 * 3)(*[int(x) for x in tile])
         _check(lib().dpd_set_tile(self._h, t))
 
+    def get_tile(self):
+        t = (ctypes.c_int32 * 3)()
+        _check(lib().dpd_get_tile(self._h, t))
+        return tuple(t)
+
+    def tune_tile(self, reps=5):
+        """Time the force kernel for the candidate tiles and keep the fastest.
+        Returns (tile, ms per force evaluation)."""
+        t = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double()
+        _check(lib().dpd_tune_tile(self._h, int(reps), t, ctypes.byref(ms)))
+        return tuple(t), ms.value
+
     def set_seed(self, seed):
         _check(lib().dpd_set_seed(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
 
@@ -193,6 +234,11 @@ class Box:
         if wp != wv:
             raise ValueError("pos and vel must both be host arrays or both device tensors")
         _check(lib().dpd_set_state(self._h, pp, vp, wp))
+
+    def init_random(self, kT, seed):
+        """Random state generated on the device (uniform positions, Maxwellian
+        velocities with the centre-of-mass velocity removed)."""
+        _check(lib().dpd_init_random(self._h, float(kT), int(seed) & 0xFFFFFFFFFFFFFFFF))
 
     # -- stepping -----------------------------------------------------------
     def build_cells(self):
@@ -263,6 +309,109 @@ class Box:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Many boxes stepped together: one launch per kernel for all boxes, one
+    captured graph for a whole run."""
+
+    def __init__(self, boxes):
+        torch = _torch()
+        self.boxes = list(boxes)
+        nb = len(self.boxes)
+        b = ctypes.c_size_t()
+        _check(lib().dpd_batch_workspace_bytes(nb, ctypes.byref(b)))
+        self.ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+        arr = (_VP * nb)(*[bx._h.value for bx in self.boxes])
+        self._h = ctypes.c_void_p()
+        _check(lib().dpd_batch_create(arr, nb, ctypes.c_void_p(self.ws.data_ptr()), b.value, _stream_ptr(torch),
+                                      ctypes.byref(self._h)))
+
+    def step(self, nsteps):
+        _check(lib().dpd_batch_step(self._h, int(nsteps)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dpd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over one torch-allocated HBM pool."""
+
+    def __init__(self, pool_bytes, max_slots=256):
+        torch = _torch()
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        self._h = ctypes.c_void_p()
+        _check(lib().dpd_server_create(ctypes.c_void_p(self.pool.data_ptr()), int(pool_bytes), int(max_slots),
+                                       _stream_ptr(torch), ctypes.byref(self._h)))
+        self._sizes = {}
+
+    def submit(self, cells, n, params, seed, nsteps, pos=None, vel=None, init_kT=1.0, init_seed=0):
+        keep = []
+        pp = vp = None
+        if pos is not None:
+            pa = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+            va = np.ascontiguousarray(vel, dtype=np.float32).reshape(-1, 3)
+            keep += [pa, va]
+            pp, vp = pa.ctypes.data_as(ctypes.c_void_p), va.ctypes.data_as(ctypes.c_void_p)
+        p = params if isinstance(params, Params) else make_params(**params)
+        r = Request(make_geom(cells, n), p, int(seed) & 0xFFFFFFFFFFFFFFFF, int(nsteps), pp, vp, float(init_kT),
+                    int(init_seed) & 0xFFFFFFFFFFFFFFFF)
+        t = ctypes.c_uint64()
+        _check(lib().dpd_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._sizes[t.value] = int(n)
+        return t.value
+
+    def pump(self, quantum):
+        ran = ctypes.c_int32()
+        _check(lib().dpd_server_pump(self._h, int(quantum), ctypes.byref(ran)))
+        return ran.value
+
+    def poll(self, ticket, want_state=False):
+        """None while running; then (result dict, pos, vel) once (pos/vel None
+        unless want_state)."""
+        res = Result()
+        n = self._sizes.get(ticket, 0)
+        pos = vel = None
+        pp = vp = None
+        if want_state:
+            pos = np.empty((n, 3), dtype=np.float32)
+            vel = np.empty((n, 3), dtype=np.float32)
+            pp, vp = pos.ctypes.data_as(ctypes.c_void_p), vel.ctypes.data_as(ctypes.c_void_p)
+        rc = lib().dpd_server_poll(self._h, int(ticket), ctypes.byref(res), pp, vp)
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        self._sizes.pop(ticket, None)
+        out = {"status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
+               "stats": res.stats.as_dict()}
+        return out, pos, vel
+
+    def counts(self):
+        q, a, ps = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().dpd_server_counts(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(ps)))
+        return q.value, a.value, ps.value
+
+    def clock(self):
+        return lib().dpd_server_clock(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dpd_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def philox(ctr4, key2):

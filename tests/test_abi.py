@@ -48,7 +48,8 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "dpd.h"
 int main(void) {
-  printf("%zu %zu %zu\\n", sizeof(dpd_geom), sizeof(dpd_params), sizeof(dpd_stats));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(dpd_geom), sizeof(dpd_params), sizeof(dpd_stats), sizeof(dpd_request),
+         sizeof(dpd_result));
   printf("%zu %zu %zu %zu\\n", offsetof(dpd_params, flow_axis), offsetof(dpd_params, flags),
          offsetof(dpd_stats, nsamples), offsetof(dpd_stats, escaped));
   return 0;
@@ -59,7 +60,8 @@ int main(void) {
     a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
-    assert sizes == [ctypes.sizeof(dpd.Geom), ctypes.sizeof(dpd.Params), ctypes.sizeof(dpd.Stats)]
+    assert sizes == [ctypes.sizeof(dpd.Geom), ctypes.sizeof(dpd.Params), ctypes.sizeof(dpd.Stats),
+                     ctypes.sizeof(dpd.Request), ctypes.sizeof(dpd.Result)]
     assert offs == [dpd.Params.flow_axis.offset, dpd.Params.flags.offset, dpd.Stats.nsamples.offset,
                     dpd.Stats.escaped.offset]
 
