@@ -41,6 +41,33 @@ def force_ops(n, rho):
     return pairs * OPS_PER_PAIR + cands * OPS_PER_CANDIDATE
 
 
+FORCE_SOURCES = ("paper_1911_04712_amd/csrc/dpd_force.hip", "paper_1911_04712_amd/csrc/dpd_device.hpp",
+                 "paper_1911_04712_amd/csrc/dpd_internal.hpp")
+
+
+def measured_traffic(workload):
+    """HBM bytes per force launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None
+    when there is none for this workload or the force-kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "force_%s_hbm_counters.md" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, _, val = line.partition(":")
+            rec[k.strip()] = val.strip()
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("force_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in rec:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -240,7 +267,7 @@ def main():
     achieved = ops / (f_ms / 1e3) / 1e12
     force_bytes = n * (32.0 + 16.0) + (n / rho) * 4.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(w.name),
                 "kernel": "k_force_tiled", "kernel_ms": round(f_ms, 4),
                 "hbm_algorithmic_GBps": round(force_bytes / (f_ms / 1e3) / 1e9, 1)}
 

@@ -160,6 +160,12 @@ def workspace_bytes(cells, n):
     return b.value
 
 
+def batch_workspace_bytes(nboxes):
+    b = ctypes.c_size_t()
+    _check(lib().dpd_batch_workspace_bytes(int(nboxes), ctypes.byref(b)))
+    return b.value
+
+
 def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1,
                 profile_bins=0, flags=0):
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f), int(flow_axis),

@@ -62,9 +62,11 @@ def test_request_alone_equals_request_in_mix():
 
 def test_admission_waits_for_memory():
     cells, n = (10, 10, 10), 3000
-    need = dpd.workspace_bytes(cells, n)
-    # room for two requests (plus the batch tables), not three
-    srv = dpd.Server(2 * need + (1 << 20), max_slots=16)
+    def a256(x):
+        return (x + 255) // 256 * 256
+    need = a256(dpd.workspace_bytes(cells, n))
+    # room for two requests plus the batch tables, not three
+    srv = dpd.Server(a256(dpd.batch_workspace_bytes(16)) + 2 * need + need // 2, max_slots=16)
     tk = [srv.submit(cells, n, P3, seed=60 + k, nsteps=40, init_kT=1.0, init_seed=k) for k in range(3)]
     srv.pump(10)
     q, a, _ = srv.counts()
