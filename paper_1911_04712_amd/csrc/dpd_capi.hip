@@ -63,7 +63,7 @@ double grid_of(const dpd_geom* g)
 constexpr int kGraphSteps = 8;          // steps per captured graph of a single box
 constexpr int kBatchGraphMax = 1024;    // a batch run of up to this many steps is one graph launch
 constexpr int kBatchGraphMin = 64;      // shorter batch runs are launched directly (no capture)
-constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kLdsLimit = 160 * 1024 - 256;   // LDS per CU less the kernels' static LDS
 
 }  // namespace
 
@@ -199,17 +199,17 @@ dpd::StepConst step_const(const dpd_box_s* b)
     return sc;
 }
 
-// Default cell tile of the LDS force kernel (measured on MI355X): 8x4x4
-// cells at solvent densities up to 4.5, 3x3x3 above.
+// Default cell tile of the LDS force kernel (measured on MI355X): 4x4x4
+// cells at solvent densities up to 4.5, 4x2x2 above.
 dpd::TileConst tile_for(const dpd_box_s* b, const int* req)
 {
     int t[3] = {req[0], req[1], req[2]};
     if (t[0] <= 0) {
         const double rho = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
         const bool dilute = rho <= 4.5;
-        t[0] = dilute ? 8 : 3;
-        t[1] = dilute ? 4 : 3;
-        t[2] = dilute ? 4 : 3;
+        t[0] = 4;
+        t[1] = dilute ? 4 : 2;
+        t[2] = dilute ? 4 : 2;
     }
     return dpd::make_tile_const(b->cells, b->n, t, 0, 0);
 }
@@ -573,8 +573,9 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         b->binned = true;
         b->keys_valid = false;
     }
-    static const int cand[][3] = {{8, 4, 4}, {4, 4, 4}, {4, 4, 8}, {8, 8, 4}, {6, 4, 4}, {4, 4, 2}, {3, 3, 3},
-                                  {4, 2, 2}, {6, 6, 4}, {2, 2, 2}, {8, 2, 2}, {4, 4, 6}};
+    static const int cand[][3] = {{4, 4, 4}, {8, 4, 4}, {4, 4, 8}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4}, {4, 2, 4},
+                                  {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4}, {8, 8, 4},
+                                  {3, 3, 2}, {6, 3, 3}};
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));

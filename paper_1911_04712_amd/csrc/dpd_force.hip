@@ -31,6 +31,15 @@
 
 namespace dpd {
 
+// Load through the global address space (the pointers in a box descriptor
+// are generic; this lets the load use the global instructions).
+__device__ __forceinline__ float4 gload4(const float4* p, int i)
+{
+    typedef float __attribute__((ext_vector_type(4))) v4;
+    const v4 t = ((const __attribute__((address_space(1))) v4*)p)[i];
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+
 __device__ __forceinline__ int wrap_cell(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
 __device__ __forceinline__ float body_force_of(float4 p, const ForceConst& fc)
@@ -57,7 +66,9 @@ __device__ __forceinline__ bool pair_fx(float4 pi, float4 vi, float4 pj, float4 
     const float xi = pair_xi(__float_as_uint(pi.w), __float_as_uint(pj.w), step, pc.k0, pc.k1);
     float rinv;
     const float fs = pair_scalar(r2, dx, dy, dz, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, rinv, xi, pc);
-    const float Fx = fs * (dx * rinv), Fy = fs * (dy * rinv), Fz = fs * (dz * rinv);
+    const bool live = r2 > 0.0f;        // coincident particles exert no force on each other
+    const float Fx = live ? fs * (dx * rinv) : 0.0f, Fy = live ? fs * (dy * rinv) : 0.0f,
+                Fz = live ? fs * (dz * rinv) : 0.0f;
     if (!(fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit)) {
         fx = fy = fz = 0;
         return false;
@@ -126,8 +137,29 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restri
 // ---------------------------------------------------------------------------
 // tiled kernel
 // ---------------------------------------------------------------------------
-constexpr int kQueue = 256;     // per-wave hit ring buffer (< 64 pending + up to 128 new)
-constexpr int kMaxSeg = 14;     // candidate runs per tile particle
+constexpr int kQueueLive = 192; // per-wave hit queue: < 64 pending + up to 2 x 64 new ...
+constexpr int kQueue = 256;     // ... then 64 slots that lanes without a hit write to
+constexpr int kRuns = 14;       // candidate runs of one home cell
+
+// Inclusive prefix sum inside each row of 16 lanes (DPP row shifts).
+__device__ __forceinline__ int row16_incl_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    return v;
+}
+
+__device__ __forceinline__ int lane_val(int v, int src_lane) { return __builtin_amdgcn_ds_bpermute(src_lane << 2, v); }
+
+// floor(x / d) for 0 <= x < 2^22, d >= 1, with inv = 1.0f / d rounded to
+// nearest: (x + 0.5) / d lies at least 0.5 / d from an integer, and the
+// float product (x + 0.5) * inv is within about x 2^-23 / d of it.
+__device__ __forceinline__ int small_div(int x, float inv)
+{
+    return (int)(((float)x + 0.5f) * inv);
+}
 
 __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const float4* sv, long long* acc,
                                           uint32_t step, const PairConst& pc, bool& bad)
@@ -147,8 +179,8 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
-                                                        int nbox)
+__global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __restrict__ desc,
+                                                             const int* __restrict__ pre, int nbox)
 {
     const int* __restrict__ pre_ = pre + kWTile * (nbox + 1);
     const int box = nbox == 1 ? 0 : find_box(pre_, nbox, (int)blockIdx.x);
@@ -164,13 +196,11 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restric
     float4* sp = (float4*)lds;                                  // staged positions (image-shifted), w = id
     float4* sv = (float4*)(lds + tc.off_sv);                    // staged velocities, w = tile index or -1
     long long* acc = (long long*)(lds + tc.off_acc);            // fixed-point force of tile particles
-    unsigned short* ps = (unsigned short*)(lds + tc.off_ps);    // tile index -> staged index
     int* cst = (int*)(lds + tc.off_cst);                        // staged cell offsets in LDS (ncs + 1)
     int* cg = (int*)(lds + tc.off_cg);                          // staged cell start in HBM (cell order)
     int4* rows = (int4*)(lds + tc.off_rows);                    // tile rows: (lds start, len, HBM start, tile start)
     unsigned* qall = (unsigned*)(lds + tc.off_q);               // per-wave hit queues
-    unsigned* segall = (unsigned*)(lds + tc.off_seg);           // per-wave candidate segments [slot][lane]
-    __shared__ int s_scr[kBlock / 64];
+    __shared__ int s_scr[kForceBlock / 64];
 
     // Consecutive tiles go to the same XCD (workgroups are dealt to the 8
     // XCDs round-robin and every box's range starts at a multiple of 8), so
@@ -185,13 +215,16 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restric
     const int P0 = min(tc.T[0], L0 - o0), P1 = min(tc.T[1], L1 - o1), P2 = min(tc.T[2], L2 - o2);
     const int S0 = P0 + 2, S1 = P1 + 2, S2 = P2 + 2;
     const int ncs = S0 * S1 * S2;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float inv_s0 = 1.0f / (float)S0, inv_s1 = 1.0f / (float)S1, inv_p1 = 1.0f / (float)P1;
     const uint32_t step = (uint32_t)d.st->step;
 
     // 1. HBM start and particle count of every staged cell (the only
     //    dependent HBM round trip before the copy), scanned into LDS offsets
     for (int lc = tid; lc < ncs; lc += blockDim.x) {
-        const int lx = lc % S0, ly = (lc / S0) % S1, lz = lc / (S0 * S1);
+        const int rr = small_div(lc, inv_s0);                  // staged row
+        const int lz = small_div(rr, inv_s1), ly = rr - lz * S1, lx = lc - rr * S0;
         const int g = wrap_cell(o0 - 1 + lx, L0) + L0 * (wrap_cell(o1 - 1 + ly, L1) + L1 * wrap_cell(o2 - 1 + lz, L2));
         const int gs = cell_start[g];
         cg[lc] = gs;
@@ -208,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restric
             const int r = r0 + lane;
             int len = 0, ls = 0, gs = 0;
             if (r < nrows) {
-                const int ly = 1 + r % P1, lz = 1 + r / P1;
+                const int qz = small_div(r, inv_p1);
+                const int ly = 1 + r - qz * P1, lz = 1 + qz;
                 const int lc1 = 1 + S0 * (ly + S1 * lz);
                 ls = cst[lc1];
                 len = cst[lc1 + P0] - ls;
@@ -236,154 +270,173 @@ __global__ __launch_bounds__(kBlock) void k_force_tiled(const BoxDesc* __restric
         return;
     }
 
-    // 3. stage the region: each staged row is at most three runs of cells
-    //    contiguous in HBM (low wrap, interior, high wrap), copied with the
-    //    periodic image shift
-    const int nsrows = S1 * S2;
-    for (int sr = wave; sr < nsrows; sr += nw) {
-        const int ly = sr % S1, lz = sr / S1;
-        const int gy = o1 - 1 + ly, gz = o2 - 1 + lz;
-        const float sy = gy < 0 ? -fc.L[1] : (gy >= L1 ? fc.L[1] : 0.0f);
-        const float sz = gz < 0 ? -fc.L[2] : (gz >= L2 ? fc.L[2] : 0.0f);
-        const bool tile_row = ly >= 1 && ly <= P1 && lz >= 1 && lz <= P2;
-        int4 rw = make_int4(0, 0, 0, 0);
-        if (tile_row) rw = rows[(ly - 1) + P1 * (lz - 1)];
-        const int lcrow = S0 * (ly + S1 * lz);
-        for (int seg = 0; seg < 3; ++seg) {
-            int lx0, lx1;
-            float sx = 0.0f;
-            if (seg == 0) {                       // lx = 0 when it wraps to the top of the box
-                if (o0 != 0) continue;
-                lx0 = 0; lx1 = 1; sx = -fc.L[0];
-            } else if (seg == 1) {                // cells inside [0, L0)
-                lx0 = (o0 == 0) ? 1 : 0;
-                lx1 = (o0 + P0 == L0) ? S0 - 1 : S0;
-            } else {                              // lx = S0-1 when it wraps to the bottom
-                if (o0 + P0 != L0) continue;
-                lx0 = S0 - 1; lx1 = S0; sx = fc.L[0];
+    // 3. stage the region, one staged particle per thread.  A staged row
+    //    (S0 cells) is at most three runs contiguous in HBM: cell lx = 0,
+    //    cells 1..S0-2 and cell S0-1; only the end cells can wrap, and they
+    //    take the periodic image shift on the way in.  Each thread finds its
+    //    row by binary search over the row starts, so all loads of a pass
+    //    are in flight together.
+    {
+        const int nsrows = S1 * S2;
+        int top = 1;
+        while (top * 2 <= nsrows) top *= 2;
+        const float shx_lo = o0 == 0 ? -fc.L[0] : 0.0f, shx_hi = o0 + P0 == L0 ? fc.L[0] : 0.0f;
+        for (int s0 = tid; s0 < S; s0 += 2 * (int)blockDim.x) {
+            int src[2], tiv[2];
+            float shx[2], shy[2], shz[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int s = min(s0 + u * (int)blockDim.x, S - 1);
+                int r = 0;
+                for (int st = top; st > 0; st >>= 1)
+                    if (r + st < nsrows && cst[(r + st) * S0] <= s) r += st;
+                const int c0 = r * S0;
+                const int lz = small_div(r, inv_s1), ly = r - lz * S1;
+                const int b1 = cst[c0 + 1], b2 = cst[c0 + S0 - 1];
+                const int seg = s < b1 ? 0 : (s < b2 ? 1 : 2);
+                const int cs = seg == 0 ? c0 : (seg == 1 ? c0 + 1 : c0 + S0 - 1);
+                src[u] = cg[cs] + (s - cst[cs]);
+                shx[u] = seg == 0 ? shx_lo : (seg == 2 ? shx_hi : 0.0f);
+                const int gy = o1 - 1 + ly, gz = o2 - 1 + lz;
+                shy[u] = gy < 0 ? -fc.L[1] : (gy >= L1 ? fc.L[1] : 0.0f);
+                shz[u] = gz < 0 ? -fc.L[2] : (gz >= L2 ? fc.L[2] : 0.0f);
+                const bool tile_row = ly >= 1 && ly <= P1 && lz >= 1 && lz <= P2;
+                tiv[u] = (tile_row && seg == 1) ? rows[(ly - 1) + P1 * (lz - 1)].w + (s - b1) : -1;
             }
-            const int gsrc = cg[lcrow + lx0];
-            const int dst0 = cst[lcrow + lx0];
-            const int cnt = cst[lcrow + lx1] - dst0;
-            for (int k = lane; k < cnt; k += 64) {
-                float4 p = pos[gsrc + k];
-                float4 v = vel[gsrc + k];
-                const int dst = dst0 + k;
-                p.x += sx;
-                p.y += sy;
-                p.z += sz;
-                int ti = -1;
-                if (tile_row && dst >= rw.x && dst < rw.x + rw.y) {
-                    ti = rw.w + (dst - rw.x);
-                    ps[ti] = (unsigned short)dst;
-                }
-                v.w = __int_as_float(ti);
-                sp[dst] = p;
-                sv[dst] = v;
+            const float4 p0 = gload4(pos, src[0]), v0 = gload4(vel, src[0]);
+            const float4 p1 = gload4(pos, src[1]), v1 = gload4(vel, src[1]);
+            sp[s0] = make_float4(p0.x + shx[0], p0.y + shy[0], p0.z + shz[0], p0.w);
+            sv[s0] = make_float4(v0.x, v0.y, v0.z, __int_as_float(tiv[0]));
+            const int s1 = s0 + (int)blockDim.x;
+            if (s1 < S) {
+                sp[s1] = make_float4(p1.x + shx[1], p1.y + shy[1], p1.z + shz[1], p1.w);
+                sv[s1] = make_float4(v1.x, v1.y, v1.z, __int_as_float(tiv[1]));
             }
         }
     }
     for (int k = tid; k < 3 * nt; k += blockDim.x) acc[k] = 0;
     __syncthreads();
 
-    // 4. candidates.  The half stencil of a tile particle, as runs of
-    //    consecutive staged particles (a row of three neighbour cells is
-    //    contiguous in LDS): own cell after i plus cell x+1; the forward rows
-    //    (y+1, z) and (y-1..y+1, z+1); and, only where they are halo cells,
-    //    the backward rows (y-1, z) and (y-1..y+1, z-1) and cell x-1.
-    //    A row or an end cell is dropped when its distance from i is >= r_c;
-    //    the bound is evaluated with the same FP32 operations as r^2 on exact
-    //    gaps, so it never drops a pair with r^2 < 1.
-    unsigned* q = qall + wave * kQueue;                 // ring buffer
-    unsigned* seg = segall + wave * (kMaxSeg * 64) + lane;
-    int qh = 0, qt = 0;                                 // wave-uniform head and tail
+    // 4. candidates, one home unit per wave at a time: ux consecutive cells
+    //    x .. x+w-1 of a tile row (w = ux, or fewer at the row's end).  All
+    //    particles of a unit share one candidate list: the unit itself and
+    //    its half stencil (cell x+w, rows (y+1, z) and (y-1..y+1, z+1) over
+    //    x-1 .. x+w), plus the backward cells that lie in the halo (pairs
+    //    that cross the tile boundary are evaluated from both tiles, each
+    //    updating only its own particle).  The list is up to 14 runs of
+    //    consecutive staged particles, one per lane of the run table:
+    //      slot 0      the unit and cell x+w (so the unit comes first)
+    //      slots 1-4   forward rows, cells x-1 .. x+w
+    //      slots 5-8   backward rows (y-1, z), (y+1, z-1), (y, z-1),
+    //                  (y-1, z-1): cells x-1 .. x+w when the row lies in the
+    //                  halo, else cell x-1 when it is a halo cell
+    //      slots 9-12  the same backward rows: cell x+w when it is a halo cell
+    //      slot 13     cell x-1 of the own row when it is a halo cell
+    //    Entries out of reach of a given particle fail the distance test.
+    //    List entries are spread over the lanes, each home particle is tested
+    //    against all of them, and hits with r < r_c are compacted into a
+    //    per-wave queue (ballot + popcount) and evaluated 64 at a time with
+    //    every lane busy.  A pair inside the tile adds F_ij to i and -F_ij to
+    //    j.  Pairs inside the unit are taken once (b after a): the unit heads
+    //    the list in cell order, so that is list position > index of a.
+    unsigned* q = qall + wave * kQueue;                 // queue, entries [0, qt); lanes without a hit
+    int qt = 0;                                         // write to q[kQueueLive + lane]; qt is wave-uniform
     bool bad = false;
-    for (int pb = wave * 64; pb < nt; pb += blockDim.x) {
-        const int p = pb + lane;
-        int si = 0, nseg = 0;
-        float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (p < nt) {
-            si = ps[p];
-            xi = sp[si];
-            const float cxf = floorf(xi.x), cyf = floorf(xi.y), czf = floorf(xi.z);
-            const int lx = min(max((int)cxf - o0 + 1, 1), P0);
-            const int ly = min(max((int)cyf - o1 + 1, 1), P1);
-            const int lz = min(max((int)czf - o2 + 1, 1), P2);
-            // exact gaps to the lower and upper faces of i's cell
-            const float gxl = xi.x - cxf, gxr = (cxf + 1.0f) - xi.x;
-            const float gyl = xi.y - cyf, gyr = (cyf + 1.0f) - xi.y;
-            const float gzl = xi.z - czf, gzr = (czf + 1.0f) - xi.z;
-            auto add = [&](int a, int b) {
-                if (a < b) {
-                    seg[nseg * 64] = (unsigned)a | ((unsigned)b << 16);
-                    ++nseg;
-                }
-            };
-            // row (dy, dz) relative to i; `mid` = include the cells of the row
-            // inside the tile, otherwise only its halo end cells
-            auto row = [&](int dy, int dz, bool mid) {
-                const float gy = dy > 0 ? gyr : (dy < 0 ? gyl : 0.0f);
-                const float gz = dz > 0 ? gzr : (dz < 0 ? gzl : 0.0f);
-                const float gyz = gy * gy;
-                if (!(fmaf(gz, gz, gyz) < 1.0f)) return;
-                const bool left = fmaf(gz, gz, fmaf(gy, gy, gxl * gxl)) < 1.0f;
-                const bool right = fmaf(gz, gz, fmaf(gy, gy, gxr * gxr)) < 1.0f;
-                const int r = S0 * ((ly + dy) + S1 * (lz + dz));
-                if (mid) {
-                    add(cst[r + (left ? lx - 1 : lx)], cst[r + (right ? lx + 2 : lx + 1)]);
-                } else {
-                    if (lx == 1 && left) add(cst[r], cst[r + 1]);
-                    if (lx == P0 && right) add(cst[r + P0 + 1], cst[r + P0 + 2]);
-                }
-            };
-            const int lcr = S0 * (ly + S1 * lz);
-            add(si + 1, cst[lcr + (gxr * gxr < 1.0f ? lx + 2 : lx + 1)]);   // own cell tail, cell x+1
-            row(1, 0, true);
-            row(-1, 1, true);
-            row(0, 1, true);
-            row(1, 1, true);
-            const int by[4] = {-1, -1, 0, 1}, bz[4] = {0, -1, -1, -1};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int ny = ly + by[k], nz = lz + bz[k];
-                row(by[k], bz[k], ny < 1 || ny > P1 || nz < 1 || nz > P2);
-            }
-            if (lx == 1) add(cst[lcr], cst[lcr + 1]);                         // cell x-1 (halo)
+    const int rj = (lane - 1) & 3;                      // stencil row of slots 1..12
+    const int fdy = (rj == 0 || rj == 3) ? 1 : (rj == 1 ? -1 : 0), fdz = rj == 0 ? 0 : 1;
+    const int rsgn = (lane == 0 || lane >= 13) ? 0 : (lane < 5 ? 1 : -1);
+    const int roff = rsgn * S0 * (fdy + S1 * fdz);      // staged-cell offset of the slot's row
+    int rs_ = 0, rl_ = 0;
+    // home units (ux consecutive cells of a tile row) go to the waves in turn
+    const int upr = (P0 + tc.ux - 1) / tc.ux;           // units per tile row
+    const int nunits = upr * nrows;
+    int hu = wave, ry = 0, rz = 0;                      // unit within its row, row (y, z): wave-uniform
+    while (hu >= upr) { hu -= upr; if (++ry == P1) { ry = 0; ++rz; } }
+    for (int un = wave; un < nunits; un += nw) {
+        const int lx = 1 + hu * tc.ux, ly = ry + 1, lz = rz + 1;
+        hu += nw;
+        while (hu >= upr) { hu -= upr; if (++ry == P1) { ry = 0; ++rz; } }
+        const int w = min(tc.ux, P0 + 1 - lx);          // cells in this unit
+        const int cown = lx + S0 * (ly + S1 * lz);
+        const int own_s = __builtin_amdgcn_readfirstlane(cst[cown]);
+        const int own_e = __builtin_amdgcn_readfirstlane(cst[cown + w]);
+        if (own_s == own_e) continue;
+        {
+            // which backward rows (slots 5-8, and 9-12) leave the tile
+            const bool yl = ly == 1, yh = ly == P1, zl = lz == 1;
+            const unsigned long long outB = ((unsigned long long)yl << 5) | ((unsigned long long)(yh || zl) << 6) |
+                                            ((unsigned long long)zl << 7) | ((unsigned long long)(yl || zl) << 8);
+            const bool xl = lx == 1, xh = lx + w - 1 == P0;
+            const unsigned long long mLeft = xl ? ((0x1E0ull & ~outB) | (1ull << 13)) : 0ull;
+            const unsigned long long mRight = xh ? (0x1E00ull & ~(outB << 4)) : 0ull;
+            const unsigned long long mOn = 0x1Full | outB | mLeft | mRight;
+            const bool left = __builtin_amdgcn_inverse_ballot_w64(mLeft);
+            const bool right = __builtin_amdgcn_inverse_ballot_w64(mRight);
+            const bool on = __builtin_amdgcn_inverse_ballot_w64(mOn);
+            // run of this slot: cells x0..x1 relative to the unit's first cell
+            const int x0 = right ? w : (lane == 0 ? 0 : -1);
+            const int x1 = left ? -1 : w;
+            const int rbase = cown + roff;
+            rs_ = cst[rbase + x0];
+            rl_ = on ? cst[rbase + x1 + 1] - rs_ : 0;
         }
-        const unsigned tag = (unsigned)si << 16;
-        int k = 0, j = 0, je = 0;
-        unsigned nxt = nseg > 0 ? seg[0] : 0u;
-        while (true) {
-            if (j >= je && k < nseg) {
-                j = (int)(nxt & 0xffffu);
-                je = (int)(nxt >> 16);
-                ++k;
-                if (k < nseg) nxt = seg[k * 64];
-            }
-            const bool a0 = j < je, a1 = j + 1 < je;
-            if (__ballot(a0) == 0ull) break;
-            const float4 x0 = sp[a0 ? j : 0];
-            const float4 x1 = sp[a1 ? j + 1 : 0];
-            const float r0 = dist2(xi.x - x0.x, xi.y - x0.y, xi.z - x0.z);
-            const float r1 = dist2(xi.x - x1.x, xi.y - x1.y, xi.z - x1.z);
-            const bool h0 = a0 && r0 < 1.0f && r0 > 0.0f;
-            const bool h1 = a1 && r1 < 1.0f && r1 > 0.0f;
-            const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
-            const int c0 = __popcll(m0);
-            if (h0) q[(qt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u))) & (kQueue - 1)] = tag | (unsigned)j;
-            if (h1) q[(qt + c0 + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u))) & (kQueue - 1)] = tag | (unsigned)(j + 1);
-            qt += c0 + __popcll(m1);
-            j += (int)a0 + (int)a1;
-            while (qt - qh >= 64) {
-                __builtin_amdgcn_wave_barrier();
-                flush_hit(q[(qh + lane) & (kQueue - 1)], sp, sv, acc, step, fc.pc, bad);
-                __builtin_amdgcn_wave_barrier();
-                qh += 64;
+        const int rs = rs_, rl = rl_;
+        const int rincl = row16_incl_scan(rl);
+        const int rpre = rincl - rl;
+        const int M = __builtin_amdgcn_readlane(rincl, 15);
+        const int delta = rs - rpre;                // staged index = list position + delta
+        for (int u0 = 0; u0 < M; u0 += 64) {
+            const int u = u0 + lane;
+            int k = 0;
+#pragma unroll
+            for (int st = 8; st > 0; st >>= 1)
+                if (lane_val(rpre, k + st) <= u) k += st;
+            const int dk = lane_val(delta, k);      // every lane takes part: source lanes must be active
+            const bool valid = u < M;
+            const int b = valid ? u + dk : own_s;
+            const float4 xb = sp[b];
+            const float bx = valid ? xb.x : 1e30f;
+            const unsigned ub = (unsigned)u;
+            const unsigned qdummy = (unsigned)(kQueueLive + lane);
+            for (int a = own_s; a < own_e; a += 2) {
+                const bool two = a + 1 < own_e;     // uniform
+                const float4 xa0 = sp[a];           // same address on every lane
+                const float4 xa1 = sp[two ? a + 1 : a];
+                const float r20 = dist2(xa0.x - bx, xa0.y - xb.y, xa0.z - xb.z);
+                const float r21 = dist2(xa1.x - bx, xa1.y - xb.y, xa1.z - xb.z);
+                // r2 < 1 (r2 == 0 adds nothing: see pair_fx), and list position
+                // after a (the unit heads the list)
+                const unsigned ia = (unsigned)(a - own_s);
+                const unsigned long long m0 = __builtin_amdgcn_ballot_w64(r20 < 1.0f) &
+                                              __builtin_amdgcn_ballot_w64(ub > ia);
+                const unsigned long long m1 = __builtin_amdgcn_ballot_w64(r21 < 1.0f) &
+                                              __builtin_amdgcn_ballot_w64(ub > ia + 1u) & (two ? ~0ull : 0ull);
+                const int c0 = __popcll(m0);
+                const unsigned s0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m0, (unsigned)qt));
+                const unsigned s1 = __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m1, (unsigned)(qt + c0)));
+                q[__builtin_amdgcn_inverse_ballot_w64(m0) ? s0 : qdummy] = ((unsigned)a << 16) | (unsigned)b;
+                q[__builtin_amdgcn_inverse_ballot_w64(m1) ? s1 : qdummy] = ((unsigned)(a + 1) << 16) | (unsigned)b;
+                qt += c0 + __popcll(m1);
+                if (qt >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    int fh = 0;
+                    do {
+                        flush_hit(q[fh + lane], sp, sv, acc, step, fc.pc, bad);
+                        fh += 64;
+                    } while (qt - fh >= 64);
+                    const unsigned rest = q[fh + lane];          // move what is left (< 64) to the front
+                    __builtin_amdgcn_wave_barrier();
+                    q[lane] = rest;
+                    __builtin_amdgcn_wave_barrier();
+                    qt -= fh;
+                }
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < qt - qh) flush_hit(q[(qh + lane) & (kQueue - 1)], sp, sv, acc, step, fc.pc, bad);
+    if (lane < qt) flush_hit(q[lane], sp, sv, acc, step, fc.pc, bad);
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
 
@@ -412,6 +465,9 @@ TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax
     const int ntc = tc.T[0] * tc.T[1] * tc.T[2];
     // capacities: mean + 6 standard deviations of a uniform fluid, rounded up
     auto cap = [](double mean) { int c = (int)std::ceil(mean + 6.0 * std::sqrt(mean + 1.0) + 16.0); return (c + 63) & ~63; };
+    // two-cell home units keep a dilute fluid's candidate list near one wave
+    // (about 19 rho entries, against 14 rho + 1 for a single cell)
+    tc.ux = (rho <= 4.5 && tc.T[0] >= 2) ? 2 : 1;
     tc.smax = smax_override > 0 ? smax_override : cap(rho * ncs_max);
     tc.pmax = pmax_override > 0 ? pmax_override : cap(rho * ntc);
     if (tc.smax > 65535) tc.smax = 65535;
@@ -420,8 +476,6 @@ TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax
     off += (size_t)tc.smax * 16;
     tc.off_acc = (int)off;
     off += (size_t)tc.pmax * 24;
-    tc.off_ps = (int)off;
-    off += ((size_t)tc.pmax * 2 + 15) & ~(size_t)15;
     tc.off_cst = (int)off;
     off += ((size_t)(ncs_max + 1) * 4 + 15) & ~(size_t)15;
     tc.off_cg = (int)off;
@@ -429,9 +483,7 @@ TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax
     tc.off_rows = (int)off;
     off += (size_t)tc.T[1] * tc.T[2] * 16;
     tc.off_q = (int)off;
-    off += (size_t)(kBlock / 64) * kQueue * 4;
-    tc.off_seg = (int)off;
-    off += (size_t)(kBlock / 64) * kMaxSeg * 64 * 4;
+    off += (size_t)(kForceBlock / 64) * kQueue * 4;
     tc.lds_bytes = (int)off;
     return tc;
 }
@@ -442,7 +494,7 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
         if (lp.total[kWPart] > 0)
             hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
-        hipLaunchKernelGGL(k_force_tiled, dim3(lp.total[kWTile]), dim3(kBlock), lp.lds_force, s, lp.desc, lp.pre,
+        hipLaunchKernelGGL(k_force_tiled, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc, lp.pre,
                            lp.nbox);
     }
     return hipGetLastError();

@@ -9,6 +9,7 @@
 namespace dpd {
 
 constexpr int kBlock = 256;             // threads per block of the streaming kernels
+constexpr int kForceBlock = 512;        // threads per workgroup of the tiled pair-force kernel
 constexpr int kScanChunk = 2048;        // cells per block of the cell-count scan
 constexpr int kIntegrateMaxBlocks = 2048;
 constexpr int kProfileMaxBins = 4096;
@@ -71,10 +72,11 @@ struct TileConst {
     int T[3];          // tile edge in cells (clamped to the box)
     int ntile[3];      // tiles per axis (the last one may be ragged)
     int ntiles;
+    int ux;            // cells per home unit of the candidate search (consecutive in x)
     int smax;          // staged particles (tile + halo) that fit the LDS buffers
     int pmax;          // tile particles that fit the accumulators
     int lds_bytes;
-    int off_sv, off_acc, off_ps, off_cst, off_cg, off_rows, off_q, off_seg;
+    int off_sv, off_acc, off_cst, off_cg, off_rows, off_q;
 };
 
 // Everything a kernel needs about one box, in device memory.  The step

@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
     DPD_BOX_OF(kWInt)
     __shared__ long long s_psum[kLdsBins];
     __shared__ int s_pcnt[kLdsBins];
-    __shared__ double s_red[kBlock / 64];
+    __shared__ double s_red[kBlock / 64][kPartials];
     const StepConst& sc = d.sc;
     const int n = d.n;
     const float4* __restrict__ pos_s = d.pos_b;
@@ -460,12 +460,19 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
     }
     if (bad) atomicOr(&d.st->nonfinite, 1);
     if (esc) atomicOr(&d.st->escaped, 1);
+    // block partials: lane tree inside each wave, then waves in index order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
-        const double t = block_sum(m[k], s_red);
-        if (threadIdx.x == 0) d.partials[lb * kPartials + k] = t;
+        const double t = wave_sum(m[k]);
+        if (lane == 0) s_red[wave][k] = t;
     }
     __syncthreads();
+    if (threadIdx.x < kPartials) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][threadIdx.x];
+        d.partials[lb * kPartials + threadIdx.x] = t;
+    }
     if (lds_prof)
         for (int b = threadIdx.x; b < nbins; b += kBlock)
             if (s_pcnt[b]) {
