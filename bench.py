@@ -11,7 +11,8 @@ kernel, bound by VALU issue) and the CPU oracle's throughput on a bounded
 sample of the same workload.
 
 Roofline accounting of the pair-force kernel (per launch, algorithmic):
-  units  = N (2 pi / 3) rho / 2 interacting pairs (each unordered pair once)
+  units  = N (2 pi / 3) rho interacting pairs (each unordered pair once: a
+           particle has (4 pi / 3) rho neighbours within r_c)
            and N 13.5 rho candidate pairs (half of the 27-cell stencil);
   ops    = 172 VALU lane-cycles per interacting pair + 7 per candidate,
            with 32-bit multiplies and transcendentals counted at their
@@ -36,7 +37,7 @@ HBM_PEAK_GBPS = 8000.0
 
 
 def force_ops(n, rho):
-    pairs = n * (2.0 * math.pi / 3.0) * rho / 2.0
+    pairs = n * (2.0 * math.pi / 3.0) * rho         # unordered pairs with r < r_c: half of (4 pi / 3) rho each
     cands = n * 13.5 * rho
     return pairs * OPS_PER_PAIR + cands * OPS_PER_CANDIDATE
 
@@ -218,6 +219,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage with HIP events")
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default cell tile of the force kernel")
+    ap.add_argument("--tile", default="", help="cell tile of the force kernel, e.g. 6,3,3 (no autotuning)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -242,6 +245,13 @@ def main():
     torch.cuda.set_device(0)
     box = dpd.Box(w.cells, n, params=params, seed=w.seed)
     box.set_state(pos, vel)
+    # the autotuner picks the force kernel's cell tile on this machine (setup,
+    # outside the timed region; tiles never change results)
+    if args.tile:
+        box.set_tile(tuple(int(t) for t in args.tile.split(",")))
+        tile = list(box.get_tile())
+    else:
+        tile = list(box.tune_tile(reps=5)[0]) if not args.no_tune else list(box.get_tile())
 
     box.step(args.warmup)
     torch.cuda.synchronize()
@@ -274,7 +284,8 @@ def main():
     out = {"metric": "particle-steps/s DPD (1 GPU)", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": w.name, "cells": list(w.cells), "particles": n, "density": rho, "a": w.a,
+           "config": {"workload": w.name, "cells": list(w.cells), "particles": n, "density": rho, "tile": tile,
+                      "a": w.a,
                       "gamma": w.gamma, "kT": w.kT, "dt": w.dt, "body_f": w.body_f, "reductions": "f64",
                       "parallelism": "single GPU"},
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
@@ -283,6 +294,25 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
+        # accuracy of the GPU result against the FP64 oracle: one step from
+        # the final state of the timed run, on both sides
+        pe, ve = box.read(dpd.POS), box.read(dpd.VEL)
+        box.set_state(pe, ve)
+        box.step(1)
+        fg, sg = box.read(dpd.FORCE).astype(np.float64), box.stats()
+        xo, vo = pe.astype(np.float64).copy(), ve.astype(np.float64).copy()
+        ido = np.arange(n, dtype=np.uint32)
+        opa = oracle.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass, body_f=w.body_f)
+        fo, so, _ = oracle.forces(xo, vo, ido, w.cells, opa, 0, w.seed)
+        rec = oracle.step(xo, vo, ido, w.cells, opa, w.seed, 0, 1, want_diag=True)[0]
+        out["accuracy"] = {
+            "against": "FP64 oracle, one step from the final state",
+            "force_max_err_over_scale": float(np.max(np.linalg.norm(fg - fo, axis=1) / np.maximum(so, 1e-300))),
+            "force_tolerance": 1e-5,
+            "momentum_abs_err": float(np.max(np.abs(np.array(sg["momentum"]) - rec["momentum"][0]))),
+            "ke_half_rel_err": float(abs(sg["ke_half"] - rec["ke_half"][0]) / rec["ke_half"][0]),
+            "kT_centred_rel_err": float(abs(sg["kT_centred"] - rec["kT_centred"][0]) / rec["kT_centred"][0]),
+        }
         sample_steps = args.cpu_steps
         x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
         ids = np.arange(n, dtype=np.uint32)

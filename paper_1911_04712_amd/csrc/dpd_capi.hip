@@ -518,6 +518,7 @@ int dpd_step(dpd_box b, int64_t nsteps)
         for (; left >= kGraphSteps; left -= kGraphSteps) HIPCHK(hipGraphLaunch(b->graph, b->stream));
     }
     HIPCHK(enqueue_steps(b->lp, left, b->stream));
+    HIPCHK(dpd::launch_fold(b->lp, b->stream));   // the last step's reductions
     b->keys_valid = true;
     b->have_force = true;
     return DPD_OK;
@@ -542,6 +543,7 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
         if (e == hipSuccess) e = dpd::launch_virial(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
         if (e == hipSuccess) e = dpd::launch_integrate(b->lp, b->stream);
+        if (e == hipSuccess) e = dpd::launch_fold(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4], b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
         for (int s = 0; s < 4 && e == hipSuccess; ++s) {
@@ -573,9 +575,9 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         b->binned = true;
         b->keys_valid = false;
     }
-    static const int cand[][3] = {{4, 4, 4}, {8, 4, 4}, {4, 4, 8}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4}, {4, 2, 4},
-                                  {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4}, {8, 8, 4},
-                                  {3, 3, 2}, {6, 3, 3}};
+    static const int cand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 4, 2}, {6, 3, 3}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4},
+                                  {4, 2, 4}, {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4},
+                                  {8, 8, 4}, {3, 3, 2}, {8, 3, 3}, {6, 4, 2}, {6, 2, 2}};
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
@@ -842,6 +844,7 @@ int dpd_batch_step(dpd_batch bt, int64_t nsteps)
         for (; left >= g; left -= g) HIPCHK(hipGraphLaunch(bt->graph, bt->stream));
     }
     HIPCHK(enqueue_steps(bt->lp, left, bt->stream));
+    HIPCHK(dpd::launch_fold(bt->lp, bt->stream));  // the last step's reductions
     // later work on each box's own stream waits for the batch
     HIPCHK(hipEventRecord(bt->done, bt->stream));
     for (dpd_box_s* b : bt->boxes) {

@@ -25,7 +25,7 @@ constexpr double kVirScale = 16777216.0;       // 2^24 units per virial unit
 // creation; read back by dpd_get_stats.
 struct DevStats {
     unsigned long long step;        // force evaluations since set_state
-    unsigned int ticket;            // last-block-done counter of the integrate kernel
+    unsigned int fold_pending;      // integrate partials not yet folded into the reductions
     int nonfinite;
     int escaped;
     int pad0;
@@ -155,6 +155,7 @@ hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_force(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
+hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s);
 TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax_override, int pmax_override);
 hipError_t force_tiled_prepare(int lds_bytes);
 hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,

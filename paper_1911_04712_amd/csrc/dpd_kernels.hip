@@ -21,8 +21,17 @@ namespace dpd {
 // a wave: lanes l0..l1 holding the same key (consecutive lanes) take one
 // atomicAdd of the run length and slots base + (l - l0).  Particles in cell
 // order mostly stay in their cell, so runs are about rho long.  Lanes with
-// valid == false must pass key = -1.  All lanes of the wave must call it.
-__device__ __forceinline__ int arrival_slot(int key, bool valid, int* __restrict__ count)
+// valid == false must pass key = -1.  All lanes of the wave must call both
+// halves (arrival_issue, then arrival_finish).
+struct ArrivalTicket {
+    int base;       // counter value taken by the run head (head lanes)
+    int my_head;    // lane of this lane's run head
+};
+
+// First half: issue the run heads' atomics.  The returned
+// value is not needed until arrival_finish, so other work can hide the
+// atomic's round trip.
+__device__ __forceinline__ ArrivalTicket arrival_issue(int key, bool valid, int* __restrict__ count)
 {
     const int lane = threadIdx.x & 63;
     const int prev = __shfl_up(key, 1, 64);
@@ -30,16 +39,24 @@ __device__ __forceinline__ int arrival_slot(int key, bool valid, int* __restrict
     const unsigned long long heads = __ballot(head);
     const unsigned long long live = __ballot(valid);
     const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const int my_head = 63 - __clzll(heads & upto);                 // valid lanes only
+    ArrivalTicket t;
+    t.my_head = 63 - __clzll(heads & upto);                         // valid lanes only
     int run_end = 64;
     const unsigned long long after = heads & ~upto;
     if (after) run_end = __ffsll((long long)after) - 1;
     const int nlive = __popcll(live);                               // valid lanes are a prefix
     if (run_end > nlive) run_end = nlive;
-    int base = 0;
-    if (head) base = atomicAdd(&count[key], run_end - lane);
-    base = __shfl(base, valid ? my_head : lane, 64);
-    return base + (lane - my_head);
+    t.base = 0;
+    if (head) t.base = atomicAdd(&count[key], run_end - lane);
+    return t;
+}
+
+// Second half: every lane of the wave must call it.
+__device__ __forceinline__ int arrival_finish(const ArrivalTicket& t, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    const int base = __shfl(t.base, valid ? t.my_head : lane, 64);
+    return base + (lane - t.my_head);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,12 +250,16 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(const BoxDesc* __restrict
     if (threadIdx.x == 0) d.bsum[lb] = v;
 }
 
+__device__ void fold_stats(const BoxDesc& d, double* s_red);
+
 __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ desc, const int* __restrict__ pre, int nbox)
 {
     DPD_BOX_OF(kWChunk)
     constexpr int per = kScanChunk / kBlock;   // 8 consecutive cells per thread
     __shared__ int scratch[kBlock / 64];
     __shared__ int wtot[kBlock / 64];
+    __shared__ double s_fold[kBlock / 64];
+    if (lb == 0) fold_stats(d, s_fold);         // the previous step's reductions, off the critical path
     const int nc = d.nc;
     int* __restrict__ count = d.count;
     // prefix of this chunk: sum of the chunk sums before it
@@ -431,12 +452,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
         }
         const int c = live ? cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
-        const int slot = arrival_slot(c, live, d.count);
-        if (!live) continue;
-        keyslot[i] = make_int2(c, slot);
-        pos_a[i] = make_float4(nx, ny, nz, x.w);
-        vel_a[i] = make_float4(vx, vy, vz, 0.0f);
-        if (fin) {
+        const ArrivalTicket tk = arrival_issue(c, live, d.count);     // atomic in flight meanwhile
+        if (live) {
+            pos_a[i] = make_float4(nx, ny, nz, x.w);
+            vel_a[i] = make_float4(vx, vy, vz, 0.0f);
+        }
+        if (live && fin) {
             m[0] += (double)vx;
             m[1] += (double)vy;
             m[2] += (double)vz;
@@ -457,9 +478,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
                 }
             }
         }
+        const int slot = arrival_finish(tk, live);
+        if (live) keyslot[i] = make_int2(c, slot);
     }
     if (bad) atomicOr(&d.st->nonfinite, 1);
     if (esc) atomicOr(&d.st->escaped, 1);
+    if (lb == 0 && threadIdx.x == 0) {   // the next force evaluation uses the next step's noise
+        d.st->step += 1;
+        d.st->fold_pending = 1;
+    }
     // block partials: lane tree inside each wave, then waves in index order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -481,17 +508,17 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             }
 }
 
-// Fold of a box's integrate partials, in block order (one workgroup per box;
-// a kernel boundary separates it from the writers).  Also advances the step
-// counter read by the next force evaluation.
-__global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict__ desc)
+// Fold of a box's integrate partials into the step's reductions, in block
+// order.  The whole workgroup calls it; it does nothing unless the integrate
+// kernel left partials to fold.  It runs in the first block of the next
+// step's scan kernel, or as its own kernel at the end of a run of steps.
+__device__ void fold_stats(const BoxDesc& d, double* s_red)
 {
-    const BoxDesc& d = desc[blockIdx.x];
-    __shared__ double s_red[kBlock / 64];
+    DevStats* st = d.st;
+    if (!st->fold_pending) return;                 // uniform: written by an earlier kernel
     const double* __restrict__ partials = d.partials;
     const int nblocks = d.nblk_int;
     const StepConst& sc = d.sc;
-    DevStats* st = d.st;
     double tot[kPartials];
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
@@ -528,13 +555,24 @@ __global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict
         st->sum_momentum[1] += mass * tot[1];
         st->sum_momentum[2] += mass * tot[2];
         st->nsamples += 1;
-        st->step += 1;
+        st->fold_pending = 0;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict__ desc)
+{
+    __shared__ double s_red[kBlock / 64];
+    fold_stats(desc[blockIdx.x], s_red);
 }
 
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s)
 {
     hipLaunchKernelGGL(k_integrate, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s)
+{
     hipLaunchKernelGGL(k_fold_stats, dim3(lp.nbox), dim3(kBlock), 0, s, lp.desc);
     return hipGetLastError();
 }

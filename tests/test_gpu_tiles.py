@@ -43,12 +43,24 @@ def test_tiled_equals_reference_one_step(cells, rho, params):
     assert np.all(np.linalg.norm(til[0] - f, axis=1) <= 1e-5 * s)
 
 
-@pytest.mark.parametrize("tile", [(1, 1, 1), (2, 3, 4), (4, 4, 4), (6, 6, 6), (16, 2, 3), (4, 4, 2)])
+@pytest.mark.parametrize("tile", [(1, 1, 1), (2, 3, 4), (4, 4, 4), (6, 6, 6), (16, 2, 3), (4, 4, 2), (3, 2, 2),
+                                  (5, 3, 2), (8, 3, 3), (1, 4, 4), (7, 1, 3)])
 def test_tile_shape_does_not_change_trajectory(tile):
     cells = (12, 10, 9)
     pos, vel = inputs.uniform_state(cells, density=3.0, seed=22)
     ref = _run(cells, pos, vel, P3, 22, 20, reference=True)
     til = _run(cells, pos, vel, P3, 22, 20, tile=tile)
+    for a, b in zip(til, ref):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("tile", [(4, 2, 2), (3, 3, 3), (5, 2, 3)])
+def test_tile_shape_dense_fluid(tile):
+    # rho = 8: one-cell home units and candidate lists longer than a wave
+    cells = (9, 7, 6)
+    pos, vel = inputs.uniform_state(cells, density=8.0, seed=26)
+    ref = _run(cells, pos, vel, P8, 26, 5, reference=True)
+    til = _run(cells, pos, vel, P8, 26, 5, tile=tile)
     for a, b in zip(til, ref):
         np.testing.assert_array_equal(a, b)
 
