@@ -227,7 +227,7 @@ int integrate_blocks(int n)
 int box_work(const BoxDesc& d, int kind)
 {
     switch (kind) {
-    case kWChunk: return d.nchunks;
+    case kWChunk: return d.nchunks + 1;                      // + one block that folds the reductions
     case kWPart: return (d.n + kBlock - 1) / kBlock;
     case kWTile: return ((d.tc.ntiles + 7) / 8) * 8;       // padded for the XCD swizzle
     default: return d.nblk_int;
@@ -238,6 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(const BoxDesc* __restrict
                                                        int nbox)
 {
     DPD_BOX_OF(kWChunk)
+    if (lb >= d.nchunks) return;
     __shared__ int scratch[kBlock / 64];
     const int base = lb * kScanChunk;
     int v = 0;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(const BoxDesc* __restrict
     if (threadIdx.x == 0) d.bsum[lb] = v;
 }
 
-__device__ void fold_stats(const BoxDesc& d, double* s_red);
+__device__ void fold_stats(const BoxDesc& d);
 
 __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ desc, const int* __restrict__ pre, int nbox)
 {
@@ -258,8 +259,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
     constexpr int per = kScanChunk / kBlock;   // 8 consecutive cells per thread
     __shared__ int scratch[kBlock / 64];
     __shared__ int wtot[kBlock / 64];
-    __shared__ double s_fold[kBlock / 64];
-    if (lb == 0) fold_stats(d, s_fold);         // the previous step's reductions, off the critical path
+    if (lb == d.nchunks) {                      // the extra block: the previous step's reductions
+        fold_stats(d);
+        return;
+    }
     const int nc = d.nc;
     int* __restrict__ count = d.count;
     // prefix of this chunk: sum of the chunk sums before it
@@ -512,14 +515,30 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
 // order.  The whole workgroup calls it; it does nothing unless the integrate
 // kernel left partials to fold.  It runs in the first block of the next
 // step's scan kernel, or as its own kernel at the end of a run of steps.
-__device__ void fold_stats(const BoxDesc& d, double* s_red)
+__device__ void fold_stats(const BoxDesc& d)
 {
+    __shared__ double s_red[kBlock / 64][kPartials];
     DevStats* st = d.st;
     if (!st->fold_pending) return;                 // uniform: written by an earlier kernel
     const double* __restrict__ partials = d.partials;
     const int nblocks = d.nblk_int;
     const StepConst& sc = d.sc;
-    double tot[kPartials];
+    // running sums the first thread updates, fetched while the partials load
+    long long vir_fx = 0;
+    double sum_kT = 0.0, sum_p = 0.0, sum_m[3] = {0.0, 0.0, 0.0};
+    unsigned long long ns = 0;
+    if (threadIdx.x == 0) {
+        vir_fx = st->virial_fx;
+        sum_kT = st->sum_kT_centred;
+        sum_p = st->sum_pressure;
+        sum_m[0] = st->sum_momentum[0];
+        sum_m[1] = st->sum_momentum[1];
+        sum_m[2] = st->sum_momentum[2];
+        ns = st->nsamples;
+    }
+    // per thread: blocks b, b + kBlock, ... in four interleaved chains; then
+    // the lane tree of each wave and the waves in index order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) {
         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -531,14 +550,22 @@ __device__ void fold_stats(const BoxDesc& d, double* s_red)
             t3 += partials[(b + 3 * kBlock) * kPartials + k];
         }
         for (; b < nblocks; b += kBlock) t0 += partials[b * kPartials + k];
-        tot[k] = block_sum((t0 + t1) + (t2 + t3), s_red);
+        const double w = wave_sum((t0 + t1) + (t2 + t3));
+        if (lane == 0) s_red[wave][k] = w;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double tot[kPartials];
+        for (int k = 0; k < kPartials; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][k];
+            tot[k] = t;
+        }
         const double mass = sc.mass;
         const double ke_half = 0.5 * mass * tot[3];
         const double ke_c = 0.5 * mass * tot[4];
         const double kT_c = 2.0 * ke_c * sc.inv_dof;
-        const double vir = (double)st->virial_fx / kVirScale;
+        const double vir = (double)vir_fx / kVirScale;
         st->virial_fx = 0;
         const double press = sc.rho * kT_c + vir * sc.inv_vol / 3.0;
         st->last[0] = mass * tot[0];
@@ -549,20 +576,19 @@ __device__ void fold_stats(const BoxDesc& d, double* s_red)
         st->last_kT_centred = kT_c;
         st->last_virial = vir;
         st->last_pressure = press;
-        st->sum_kT_centred += kT_c;
-        st->sum_pressure += press;
-        st->sum_momentum[0] += mass * tot[0];
-        st->sum_momentum[1] += mass * tot[1];
-        st->sum_momentum[2] += mass * tot[2];
-        st->nsamples += 1;
+        st->sum_kT_centred = sum_kT + kT_c;
+        st->sum_pressure = sum_p + press;
+        st->sum_momentum[0] = sum_m[0] + mass * tot[0];
+        st->sum_momentum[1] = sum_m[1] + mass * tot[1];
+        st->sum_momentum[2] = sum_m[2] + mass * tot[2];
+        st->nsamples = ns + 1;
         st->fold_pending = 0;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict__ desc)
 {
-    __shared__ double s_red[kBlock / 64];
-    fold_stats(desc[blockIdx.x], s_red);
+    fold_stats(desc[blockIdx.x]);
 }
 
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s)
