@@ -122,8 +122,13 @@ def bench_batched(nboxes=64, steps=500, tune=True):
         b.step(steps)
     _sync()
     t_boxgraph = time.perf_counter() - t0
-    # batched: one launch of one captured graph for every box and step
+    # batched: one launch of one captured graph for every box and step; the
+    # batch autotuner may replace the per-box tiles by one tile for all boxes
     batch = dpd.Batch(boxes)
+    reset()
+    t_bt = time.perf_counter()
+    btile, _ = batch.tune(reps=3)
+    t_bt = time.perf_counter() - t_bt
     reset()
     batch.step(steps)                  # capture + first run
     _sync()
@@ -142,8 +147,9 @@ def bench_batched(nboxes=64, steps=500, tune=True):
             "plain_loop": ps / t_plain, "per_box_graph_loop": ps / t_boxgraph,
             "speedup_vs_plain": t_plain / t_batch, "speedup_vs_per_box_graph": t_boxgraph / t_batch,
             "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4), "per_box_graph": round(t_boxgraph, 4),
-                        "autotune": round(t_tune, 3)},
-            "distinct_tiles": sorted({str(t) for t in tiles.values()}), "batched_equals_plain": same}
+                        "autotune": round(t_tune, 3), "batch_autotune": round(t_bt, 3)},
+            "distinct_tiles": sorted({str(t) for t in tiles.values()}),
+            "batch_tile": list(btile) if btile else "per-box", "batched_equals_plain": same}
 
 
 def bench_served(nreq=1000, quantum=50, pool_gb=32, max_slots=256):

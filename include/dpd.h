@@ -241,9 +241,22 @@ int dpd_batch_workspace_bytes(int32_t nboxes, size_t* bytes);
 int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t ws_bytes, void* hip_stream,
                      dpd_batch* out);
 
-/* Advance every box by nsteps.  Every box needs params, seed and state and
- * must not hold a bare cell list (dpd_build_cells / dpd_tune_tile without a
- * step since).  Picks up each box's current parameters and tile.  Waits for
+/* Batch autotuner: bins every box once and times the batched pair-force
+ * launch (`reps` launches per configuration, HIP events on the batch stream)
+ * for the boxes' current tiles and for each tile shape of the single-box
+ * list applied to all boxes (skipping shapes whose LDS does not fit a CU
+ * for some box); keeps the fastest.  tile_out receives the uniform tile, or
+ * {0, 0, 0} when the boxes' own tiles were fastest; *ms_out (may be NULL) the
+ * mean ms per batched force evaluation.  Boxes must have params, seed and
+ * state and must not hold a bare cell list; afterwards every box holds its
+ * cell list (dpd_batch_step then starts from it).  No result changes: the
+ * state does not advance and results do not depend on the tile.
+ * Synchronises. */
+int dpd_batch_tune(dpd_batch batch, int32_t reps, int32_t tile_out[3], double* ms_out);
+
+/* Advance every box by nsteps.  Every box needs params, seed and state;
+ * either no box or every box holds a bare cell list (dpd_build_cells,
+ * dpd_tune_tile or dpd_batch_tune without a step since).  Picks up each box's current parameters and tile.  Waits for
  * work pending on the boxes' streams; later work on a box's stream waits for
  * the batch.  Runs of 64..1024 steps are one launch of a captured graph
  * (kept for the next call of the same length); shorter runs are launched

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <array>
 #include <vector>
 
 #include "dpd.h"
@@ -64,6 +65,11 @@ constexpr int kGraphSteps = 8;          // steps per captured graph of a single 
 constexpr int kBatchGraphMax = 1024;    // a batch run of up to this many steps is one graph launch
 constexpr int kBatchGraphMin = 64;      // shorter batch runs are launched directly (no capture)
 constexpr size_t kLdsLimit = 160 * 1024 - 256;   // LDS per CU less the kernels' static LDS
+
+// Tile shapes the autotuners try (cells per edge).
+constexpr int kTuneCand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 4, 2}, {6, 3, 3}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4},
+                                {4, 2, 4}, {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4},
+                                {8, 8, 4}, {3, 3, 2}, {8, 3, 3}, {6, 4, 2}, {6, 2, 2}};
 
 }  // namespace
 
@@ -575,9 +581,7 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         b->binned = true;
         b->keys_valid = false;
     }
-    static const int cand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 4, 2}, {6, 3, 3}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4},
-                                  {4, 2, 4}, {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4},
-                                  {8, 8, 4}, {3, 3, 2}, {8, 3, 3}, {6, 4, 2}, {6, 2, 2}};
+    const auto& cand = kTuneCand;
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
@@ -817,15 +821,101 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
     return DPD_OK;
 }
 
+int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_out)
+{
+    if (!bt || !tile_out) return fail(DPD_EINVAL, "dpd_batch_tune: null argument");
+    if (reps < 1 || reps > 1000) return fail(DPD_EINVAL, "dpd_batch_tune: reps must be in 1..1000");
+    for (size_t i = 0; i < bt->boxes.size(); ++i) {
+        dpd_box_s* b = bt->boxes[i];
+        if (!ready(b)) return fail(DPD_ESTATE, "dpd_batch_tune: box %zu lacks params, seed or state", i);
+        if (b->binned) return fail(DPD_ESTATE, "dpd_batch_tune: box %zu holds a bare cell list", i);
+        if (b->params.flags & DPD_FLAG_REFERENCE_FORCE)
+            return fail(DPD_EINVAL, "dpd_batch_tune: box %zu takes the reference force path", i);
+    }
+    for (dpd_box_s* b : bt->boxes) HIPCHK(hipStreamSynchronize(b->stream));
+    int rc = batch_refresh(bt);
+    if (rc) return rc;
+    HIPCHK(dpd::launch_bin(bt->lp, bt->stream));   // cell lists of the current state, for every timing
+    for (dpd_box_s* b : bt->boxes) {
+        b->binned = true;
+        b->keys_valid = false;
+        b->have_force = false;
+        b->graph_dirty = true;
+    }
+    std::vector<std::array<int, 3>> saved;
+    for (dpd_box_s* b : bt->boxes) saved.push_back({b->tile_req[0], b->tile_req[1], b->tile_req[2]});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bt3[3] = {0, 0, 0};
+    bool have_best = false;
+    const int ncand = (int)(sizeof kTuneCand / sizeof kTuneCand[0]);
+    for (int ci = -1; ci < ncand && rc == DPD_OK; ++ci) {      // -1: the boxes' own tiles
+        bool fits = true;
+        for (size_t i = 0; i < bt->boxes.size() && fits; ++i) {
+            dpd_box_s* b = bt->boxes[i];
+            const int* t = ci < 0 ? saved[i].data() : kTuneCand[ci];
+            fits = (size_t)tile_for(b, t).lds_bytes <= kLdsLimit;
+        }
+        if (!fits) continue;
+        for (size_t i = 0; i < bt->boxes.size() && rc == DPD_OK; ++i) {
+            dpd_box_s* b = bt->boxes[i];
+            const int* t = ci < 0 ? saved[i].data() : kTuneCand[ci];
+            for (int k = 0; k < 3; ++k) b->tile_req[k] = t[k];
+            rc = push_desc(b);
+        }
+        if (rc == DPD_OK) rc = batch_refresh(bt);
+        if (rc) break;
+        float ms = 0.0f;
+        hipError_t e = dpd::launch_force(bt->lp, bt->stream);     // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, bt->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(bt->lp, bt->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, bt->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(DPD_EDEVICE, "dpd_batch_tune: %s", hipGetErrorString(e));
+            break;
+        }
+        const double per = ms / reps;
+        if (per < best) {
+            best = per;
+            have_best = true;
+            for (int k = 0; k < 3; ++k) bt3[k] = ci < 0 ? 0 : kTuneCand[ci][k];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // apply the winner (or restore the boxes' own tiles)
+    int rc2 = DPD_OK;
+    for (size_t i = 0; i < bt->boxes.size() && rc2 == DPD_OK; ++i) {
+        dpd_box_s* b = bt->boxes[i];
+        const bool uniform = rc == DPD_OK && have_best && bt3[0] > 0;
+        for (int k = 0; k < 3; ++k) b->tile_req[k] = uniform ? bt3[k] : saved[i][k];
+        rc2 = push_desc(b);
+    }
+    if (rc2 == DPD_OK) rc2 = batch_refresh(bt);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    for (int k = 0; k < 3; ++k) tile_out[k] = bt3[k];
+    if (ms_out) *ms_out = best;
+    return DPD_OK;
+}
+
 int dpd_batch_step(dpd_batch bt, int64_t nsteps)
 {
     if (!bt) return fail(DPD_EINVAL, "dpd_batch_step: null batch");
     if (nsteps < 0) return fail(DPD_EINVAL, "dpd_batch_step: nsteps < 0");
+    size_t nbinned = 0;
     for (size_t i = 0; i < bt->boxes.size(); ++i) {
         dpd_box_s* b = bt->boxes[i];
         if (!ready(b)) return fail(DPD_ESTATE, "dpd_batch_step: box %zu lacks params, seed or state", i);
-        if (b->binned) return fail(DPD_ESTATE, "dpd_batch_step: box %zu holds a bare cell list; step it once alone", i);
+        nbinned += b->binned ? 1 : 0;
     }
+    if (nbinned != 0 && nbinned != bt->boxes.size())
+        return fail(DPD_ESTATE, "dpd_batch_step: %zu of %zu boxes hold a bare cell list; step them once alone",
+                    nbinned, bt->boxes.size());
     if (nsteps == 0) return DPD_OK;
     for (dpd_box_s* b : bt->boxes) HIPCHK(hipStreamSynchronize(b->stream));
     int rc = batch_refresh(bt);
@@ -834,6 +924,11 @@ int dpd_batch_step(dpd_batch bt, int64_t nsteps)
     // a single launch; longer runs replay it.  Short runs (a serving quantum
     // on a changing set of boxes) are launched directly.
     int64_t left = nsteps;
+    if (nbinned) {                       // first step reuses the cell lists
+        HIPCHK(enqueue_step_tail(bt->lp, bt->stream));
+        for (dpd_box_s* b : bt->boxes) b->binned = false;
+        --left;
+    }
     if (nsteps >= kBatchGraphMin) {
         const int64_t g = nsteps < kBatchGraphMax ? nsteps : kBatchGraphMax;
         if (bt->graph_steps != g) {

@@ -84,6 +84,8 @@ SIGNATURES = {
     "dpd_batch_create": ([ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)],
                          ctypes.c_int),
     "dpd_batch_step": ([_VP, _I64], ctypes.c_int),
+    "dpd_batch_tune": ([_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+                       ctypes.c_int),
     "dpd_batch_destroy": ([_VP], ctypes.c_int),
     "dpd_init_random": ([_VP, ctypes.c_double, ctypes.c_uint64], ctypes.c_int),
     "dpd_server_create": ([_VP, ctypes.c_size_t, ctypes.c_int32, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
@@ -335,6 +337,14 @@ class Batch:
 
     def step(self, nsteps):
         _check(lib().dpd_batch_step(self._h, int(nsteps)))
+
+    def tune(self, reps=5):
+        """Batch autotuner: returns (uniform tile or None when the boxes'
+        own tiles were fastest, ms per batched force evaluation)."""
+        t = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double()
+        _check(lib().dpd_batch_tune(self._h, int(reps), t, ctypes.byref(ms)))
+        return (tuple(t) if t[0] > 0 else None), ms.value
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

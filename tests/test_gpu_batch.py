@@ -98,15 +98,55 @@ def test_batch_errors():
     assert e.value.code == dpd.ESTATE
     pos, vel = inputs.uniform_state((4, 4, 4), n=50, seed=1)
     b1.set_state(pos, vel)
+    b2 = dpd.Box((5, 4, 4), 60, params=dpd.make_params(), seed=2)
+    b2.set_state(*inputs.uniform_state((5, 4, 4), n=60, seed=2))
+    pair = dpd.Batch([b1, b2])
     b1.build_cells()
     with pytest.raises(dpd.DPDError) as e:
-        batch.step(1)                       # bare cell list
+        pair.step(1)                        # one box holds a bare cell list, the other not
     assert e.value.code == dpd.ESTATE
+    batch.step(1)                           # every box of this batch does: it starts from the lists
     b1.step(1)
     batch.step(2)
-    assert b1.stats()["step"] == 3
+    assert b1.stats()["step"] == 4
+    pair.close()
     batch.close()
     b1.close()
+    b2.close()
+
+
+def test_batch_tuner_changes_no_bits():
+    cells = [(9, 8, 8), (16, 12, 10), (6, 6, 6), (24, 9, 11)]
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    states = [inputs.uniform_state(c, density=3.0, seed=60 + k) for k, c in enumerate(cells)]
+    alone = []
+    for k, (c, (p, v)) in enumerate(zip(cells, states)):
+        b = dpd.Box(c, len(p), params=params, seed=60 + k)
+        b.set_state(p, v)
+        b.step(9)
+        alone.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE)))
+        b.close()
+    boxes = []
+    for k, (c, (p, v)) in enumerate(zip(cells, states)):
+        b = dpd.Box(c, len(p), params=params, seed=60 + k)
+        b.set_state(p, v)
+        boxes.append(b)
+    batch = dpd.Batch(boxes)
+    batch.step(4)
+    tile, ms = batch.tune(reps=2)
+    assert ms > 0
+    if tile is not None:
+        assert all(b.get_tile() == tuple(min(t, c) for t, c in zip(tile, b_cells))
+                   for b, b_cells in zip(boxes, cells))
+    batch.step(5)
+    for b, ref in zip(boxes, alone):
+        assert b.stats()["step"] == 9
+        np.testing.assert_array_equal(b.read(dpd.POS), ref[0])
+        np.testing.assert_array_equal(b.read(dpd.VEL), ref[1])
+        np.testing.assert_array_equal(b.read(dpd.FORCE), ref[2])
+    batch.close()
+    for b in boxes:
+        b.close()
 
 
 def test_autotuner_picks_a_tile_and_changes_no_bits():
