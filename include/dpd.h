@@ -97,7 +97,7 @@ typedef struct {
 /* Model parameters (Sec. 2.1, Eqs. 3-5; Sec. 4.2, Eq. 11).
  * sigma = sqrt(2 gamma kT) is derived.  Required: dt > 0, mass > 0,
  * gamma >= 0, kT >= 0, all finite; flow_axis != grad_axis in {0,1,2};
- * profile_bins in [0, 4096]. */
+ * profile_bins in [0, 4096]; 0 <= kexp <= 1. */
 typedef struct {
     double a;             /* conservative amplitude                                */
     double gamma;         /* dissipative coefficient                               */
@@ -111,6 +111,10 @@ typedef struct {
     int32_t grad_axis;
     int32_t profile_bins; /* slabs along grad_axis for the flow profile (0 = off)  */
     int32_t flags;        /* DPD_FLAG_*                                            */
+    double kexp;          /* exponent k of the random-term kernel w_R = (1 - r)^k;
+                             the dissipative kernel is w_D = w_R^2 and the
+                             conservative weight stays 1 - r (Sec. 2.1).
+                             0 < k <= 1; 0 selects k = 1                           */
 } dpd_params;
 
 /* Diagnostics, all reduced in FP64 on the GPU in a fixed order.

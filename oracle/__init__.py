@@ -17,7 +17,7 @@ _lib = None
 class Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
-                ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32)]
+                ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32), ("kexp", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
@@ -64,9 +64,10 @@ def lib():
     return _lib
 
 
-def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1):
+def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1, kexp=1.0):
+    """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1)."""
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f),
-                  int(flow_axis), int(grad_axis))
+                  int(flow_axis), int(grad_axis), float(kexp))
 
 
 def philox4x32_10(ctr, key):

@@ -13,7 +13,7 @@
  *   - DPD force sum, C/D/R terms ......... Sec. 2.1, Eqs. (2)-(5), with the
  *                                          fluctuation-dissipation relation
  *                                          w_D = w_R^2, sigma^2 = 2 gamma kT
- *                                          and kernel exponent k = 1
+ *                                          and the kernel w_R = w^k
  *   - cell lists (edge r_c, sort by cell)  Sec. 3.2
  *   - fused velocity-Verlet (kick, drift)  Sec. 3.1, time-stepping step 5
  *   - periodic Poiseuille body force ..... Sec. 4.2, Eq. (11)
@@ -48,6 +48,8 @@ typedef struct {
     double body_f;     /* periodic-Poiseuille amplitude f (Eq. 11); 0=off  */
     int32_t flow_axis; /* axis the body force acts along                   */
     int32_t grad_axis; /* axis whose coordinate selects the force sign     */
+    double kexp;       /* kernel exponent k of w_R = w^k, 0 < k <= 1 (Sec. 2.1);
+                          0 means k = 1                                   */
 } orc_params;
 
 typedef struct {
@@ -218,8 +220,9 @@ int orc_bin(int64_t n, const float* pos3, const int32_t cells[3], int64_t* order
 /* ------------------------------------------------------------------ */
 
 /* Force on i from j.  Minimum-image displacement r_ij = r_i - r_j, unit
- * vector e_ij = r_ij / r_ij, weight w = 1 - r (r_c = 1, Eq. 4), w_R = w and
- * w_D = w^2 (k = 1), v_ij = v_i - v_j, sigma = sqrt(2 gamma kT), and the
+ * vector e_ij = r_ij / r_ij, weight w = 1 - r (r_c = 1, Eq. 4) of the
+ * conservative term, random-term kernel w_R = w^k and dissipative kernel
+ * w_D = w_R^2 (Sec. 2.1), v_ij = v_i - v_j, sigma = sqrt(2 gamma kT), and the
  * white noise discretised as xi / sqrt(dt).  Pairs at r >= r_c, and a pair
  * at r = 0 (where e_ij is undefined), contribute nothing.
  * Outputs: F (total pair force on i), Fc (conservative part), mag (sum of
@@ -246,9 +249,10 @@ int orc_pair_force(const double ri[3], const double rj[3], const double vi[3], c
     double ev = e[0] * (vi[0] - vj[0]) + e[1] * (vi[1] - vj[1]) + e[2] * (vi[2] - vj[2]);
     double sigma = sqrt(2.0 * p->gamma * p->kT);
     double xi = orc_xi(id_i, id_j, step, seed);
+    double wr = (p->kexp == 0.0 || p->kexp == 1.0) ? w : pow(w, p->kexp);
     double fC = p->a * w;
-    double fD = -p->gamma * w * w * ev;
-    double fR = sigma * w * xi / sqrt(p->dt);
+    double fD = -p->gamma * wr * wr * ev;
+    double fR = sigma * wr * xi / sqrt(p->dt);
     double fs = fC + fD + fR;
     for (int k = 0; k < 3; ++k) {
         F[k] = fs * e[k];
@@ -336,6 +340,7 @@ static int orc_check(const int32_t cells[3], const orc_params* p)
     for (int k = 0; k < 3; ++k)
         if (cells[k] < 3) return -1;      /* 27 distinct neighbour cells need L >= 3 */
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || p->gamma < 0.0 || p->kT < 0.0) return -1;
+    if (!(p->kexp >= 0.0 && p->kexp <= 1.0)) return -1;
     if (p->flow_axis < 0 || p->flow_axis > 2 || p->grad_axis < 0 || p->grad_axis > 2) return -1;
     if (p->flow_axis == p->grad_axis) return -1;
     return 0;

@@ -169,6 +169,8 @@ dpd::ForceConst force_const(const dpd_box_s* b)
     fc.pc.sig_rdt = (float)(std::sqrt(2.0 * p.gamma * p.kT) / std::sqrt(p.dt));
     fc.pc.k0 = (uint32_t)b->seed;
     fc.pc.k1 = (uint32_t)(b->seed >> 32);
+    fc.pc.kgen = (p.kexp != 0.0 && p.kexp != 1.0) ? 1 : 0;
+    fc.pc.kexp = fc.pc.kgen ? (float)p.kexp : 1.0f;
     for (int k = 0; k < 3; ++k) {
         fc.L[k] = b->L[k];
         fc.cells[k] = b->cells[k];
@@ -399,6 +401,7 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
     if (p->profile_bins < 0 || p->profile_bins > dpd::kProfileMaxBins)
         return fail(DPD_EINVAL, "dpd_set_params: profile_bins must be in [0, %d]", dpd::kProfileMaxBins);
     if (p->flags & ~(DPD_FLAG_VIRIAL | DPD_FLAG_REFERENCE_FORCE)) return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
+    if (!(p->kexp >= 0.0 && p->kexp <= 1.0)) return fail(DPD_EINVAL, "dpd_set_params: kexp must be in [0, 1]");
     const double sig = std::sqrt(2.0 * p->gamma * p->kT) / std::sqrt(p->dt);
     if (!std::isfinite(sig) || sig > 1e8 || std::fabs(p->a) > 1e8 || p->gamma > 1e8)
         return fail(DPD_EINVAL, "dpd_set_params: parameters out of the FP32 force range");

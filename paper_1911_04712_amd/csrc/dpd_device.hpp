@@ -79,10 +79,42 @@ struct PairConst {
     float gamma;      // dissipative coefficient
     float sig_rdt;    // sigma / sqrt(dt)
     uint32_t k0, k1;  // Philox key = seed
+    float kexp;       // exponent k of the random-term kernel w_R = w^k
+    int kgen;         // 0: k = 1 (w_R = w), 1: general k
 };
+
+// Error-free sum a + b = s + e (Knuth's TwoSum).
+__device__ __forceinline__ float two_sum(float a, float b, float& e)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+// 1 - r for a pair at r < 1, accurate to a few ulp of itself even near the
+// cutoff: 1 - r^2 from the exact squares of the (exact) displacement
+// components (fma two-products and TwoSum), then divided by 1 + r.  The
+// plain 1 - r2 * rsqrt(r2) has an absolute error of ~1e-7, which a kernel
+// w^k with k < 1 amplifies by k w^(k-1) near the cutoff.
+__device__ __forceinline__ float one_minus_r(float dx, float dy, float dz, float r)
+{
+    const float p0 = dx * dx, p1 = dy * dy, p2 = dz * dz;
+    const float e0 = fmaf(dx, dx, -p0), e1 = fmaf(dy, dy, -p1), e2 = fmaf(dz, dz, -p2);
+    float c1, c2;
+    const float s1 = two_sum(p0, p1, c1);
+    const float s2 = two_sum(s1, p2, c2);
+    // 1 - s2 is exact for s2 in [1/2, 1] (Sterbenz); below 1/2, w > 0.29 and
+    // its rounding is already relatively small
+    const float t = (1.0f - s2) - (((e0 + e1) + e2) + (c1 + c2));
+    return t * __builtin_amdgcn_rcpf(1.0f + r);
+}
 
 // Scalar pair force along e_ij for r2 in (0, 1): returns F_ij / e_ij
 // (the vector force is ret * d * rinv).  d = r_i - r_j, dv = v_i - v_j.
+// F = a w - gamma w_R^2 (e.v) + sigma w_R xi / sqrt(dt), w = 1 - r,
+// w_R = w^k (Sec. 2.1); k = 1 keeps the one-multiply form.  For general k,
+// w_R = 2^(k log2 w) with the hardware log2 / exp2 on an accurate w.
 __device__ __forceinline__ float pair_scalar(float r2, float dx, float dy, float dz, float dvx, float dvy,
                                              float dvz, float& rinv, float xi, const PairConst& pc)
 {
@@ -90,8 +122,13 @@ __device__ __forceinline__ float pair_scalar(float r2, float dx, float dy, float
     const float r = r2 * rinv;
     const float w = 1.0f - r;
     const float ev = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx)) * rinv;   // e_ij . v_ij
-    const float inner = fmaf(pc.sig_rdt, xi, fmaf(-pc.gamma * w, ev, pc.a));
-    return w * inner;
+    if (!pc.kgen) {
+        const float inner = fmaf(pc.sig_rdt, xi, fmaf(-pc.gamma * w, ev, pc.a));
+        return w * inner;
+    }
+    const float wa = fmaxf(one_minus_r(dx, dy, dz, r), 0.0f);   // an exact r^2 >= 1 rounded below gives 0
+    const float wr = __builtin_amdgcn_exp2f(pc.kexp * __builtin_amdgcn_logf(wa));
+    return fmaf(wr, fmaf(pc.sig_rdt, xi, (-pc.gamma * wr) * ev), pc.a * w);
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz)

@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
                 ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32),
-                ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32), ("kexp", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -169,9 +169,10 @@ def batch_workspace_bytes(nboxes):
 
 
 def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1,
-                profile_bins=0, flags=0):
+                profile_bins=0, flags=0, kexp=1.0):
+    """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1)."""
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f), int(flow_axis),
-                  int(grad_axis), int(profile_bins), int(flags))
+                  int(grad_axis), int(profile_bins), int(flags), float(kexp))
 
 
 def _as_arg(arr, dtype, shape_tail):

@@ -1,0 +1,119 @@
+"""Viscosity of the DPD fluid from periodic (reverse) Poiseuille flow.
+
+The paper measures the viscosity of its fluids with Poiseuille flow
+(Sec. 4.1, Table 1: eta = rho f R^2 / (8 u_avg) in a pipe) and introduces the
+wall-free periodic form (Sec. 4.2, Eq. 11): a body force -f along the flow
+axis where the gradient coordinate is <= L/2 and +f above drives two
+counter-flowing parabolas.  For a Newtonian fluid of mass density rho the
+flow-axis velocity is, with s = y mod L/2,
+
+    v(y) = -/+ rho f s (L/2 - s) / (2 eta)   (lower / upper half),
+
+so eta follows from a least-squares fit of the measured profile to that
+shape.  The profile is accumulated on the GPU (fixed point, per slab of the
+gradient axis, time-centred velocities) in blocks whose scatter gives the
+statistical error.
+
+    python -m paper_1911_04712_amd.viscosity      # the r_c = 1 rows of Table 1
+"""
+import json
+import math
+import sys
+
+import numpy as np
+
+from . import dpd
+
+# Table 1 rows with r_c = 1: DPD parameters, the paper's measured range and
+# the literature value it compares with.
+TABLE1_RC1 = [
+    dict(a=0.9375, gamma=115.6, rho=4, k=1.0, kT=0.05, dt=0.01, eta_paper=(4.4, 4.6), eta_ref=4.7),
+    dict(a=6.0, gamma=20.0, rho=3, k=0.15, kT=0.1, dt=0.002, eta_paper=(8.0, 8.3), eta_ref=8.1),
+    dict(a=25.0, gamma=6.75, rho=3, k=1.0, kT=1.0, dt=0.04, eta_paper=(0.89, 0.9), eta_ref=0.91),
+    dict(a=18.75, gamma=4.5, rho=4, k=1.0, kT=1.0, dt=0.005, eta_paper=(1.07, 1.08), eta_ref=1.08),
+    dict(a=18.75, gamma=4.5, rho=4, k=0.25, kT=1.0, dt=0.005, eta_paper=(2.44, 2.45), eta_ref=2.59),
+    dict(a=0.0, gamma=20.25, rho=6, k=1.0, kT=0.5, dt=0.01, eta_paper=(2.08, 2.1), eta_ref=2.09),
+]
+
+
+def _shape(nb, L):
+    """Bin average of sign(y) s (L/2 - s), s = y mod L/2, over nb slabs."""
+    g = np.empty(nb)
+    for i in range(nb):
+        yy = np.linspace(i * L / nb, (i + 1) * L / nb, 201)
+        s = np.mod(yy, L / 2)
+        g[i] = np.mean(np.where(yy <= L / 2, -1.0, 1.0) * s * (L / 2 - s))
+    return g
+
+
+def fit_eta(profiles, rho, f, L):
+    """profiles: blocks x slabs of mean flow velocity.  Returns (eta, its
+    standard error, reduced chi^2 of the parabola fit)."""
+    prof = np.asarray(profiles)
+    mean = prof.mean(axis=0)
+    err = prof.std(axis=0, ddof=1) / math.sqrt(len(prof))
+    g = _shape(len(mean), L)
+    w = 1.0 / np.maximum(err, 1e-12) ** 2
+    c = np.sum(w * g * mean) / np.sum(w * g * g)           # c = rho f / (2 eta)
+    dc = 1.0 / math.sqrt(np.sum(w * g * g))
+    chi2 = np.sum(w * (mean - c * g) ** 2) / (len(mean) - 1)
+    eta = rho * f / (2.0 * c)
+    return eta, eta * dc / abs(c), chi2
+
+
+def measure(a, gamma, rho, k, kT, dt, eta_guess, f=None, cells=(16, 16, 16), warm_tau=10.0, blocks=10,
+            block_tau=3.0, seed=1):
+    """Periodic-Poiseuille viscosity on the GPU.  Flow along x, gradient along
+    y (cells[1] slabs of one cell).  The expected viscosity eta_guess sets
+    only the drive and the run length: f gives a peak flow of about
+    0.2 sqrt(kT), and the warm-up and each of the averaging blocks last
+    warm_tau and block_tau momentum relaxation times rho (L/2)^2 / (pi^2 eta).
+    eta_err is the block-scatter error of one run; slow flow fluctuations
+    make runs with other seeds scatter about three times more, so main()
+    reports the scatter over seeds."""
+    L = float(cells[1])
+    n = int(round(rho * cells[0] * cells[1] * cells[2]))
+    tau = rho * (L / 2) ** 2 / (math.pi ** 2 * eta_guess)
+    if f is None:
+        f = 0.2 * math.sqrt(kT) * 32.0 * eta_guess / (rho * L * L)
+    warm_steps = int(round(warm_tau * tau / dt))
+    block_steps = max(100, int(round(block_tau * tau / dt)))
+    nb = cells[1]
+    p = dpd.make_params(a=a, gamma=gamma, kT=kT, dt=dt, body_f=f, flow_axis=0, grad_axis=1, profile_bins=nb,
+                        kexp=k)
+    box = dpd.Box(cells, n, params=p, seed=seed)
+    try:
+        box.init_random(kT, seed)
+        box.step(warm_steps)
+        profiles = []
+        for _ in range(blocks):
+            box.reset_accumulators()
+            box.step(block_steps)
+            sv, cn = box.profile()
+            profiles.append(sv / np.maximum(cn, 1.0))
+        st = box.stats()
+    finally:
+        box.close()
+    eta, deta, chi2 = fit_eta(profiles, rho, f, L)
+    return {"eta": eta, "eta_err": deta, "chi2": chi2, "f": f, "particles": n, "cells": list(cells),
+            "steps": warm_steps + blocks * block_steps,
+            "kT_centred": st["sum_kT_centred"] / max(st["nsamples"], 1)}      # mean over the last block
+
+
+def main(argv=None):
+    seeds = range(1, 5)
+    for row in TABLE1_RC1:
+        par = {k: row[k] for k in ("a", "gamma", "rho", "k", "kT", "dt")}
+        runs = [measure(**par, eta_guess=sum(row["eta_paper"]) / 2, seed=s) for s in seeds]
+        etas = np.array([r["eta"] for r in runs])
+        print(json.dumps({"params": par, "eta": float(etas.mean()),
+                          "eta_err": float(etas.std(ddof=1) / math.sqrt(len(etas))),
+                          "eta_runs": [round(float(e), 4) for e in etas], "eta_paper": row["eta_paper"],
+                          "eta_ref": row["eta_ref"], "cells": runs[0]["cells"], "particles": runs[0]["particles"],
+                          "steps_per_run": runs[0]["steps"], "f": runs[0]["f"],
+                          "kT_centred": float(np.mean([r["kT_centred"] for r in runs]))}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

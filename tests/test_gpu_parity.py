@@ -35,7 +35,7 @@ def _box(cells, pos, vel, params, seed):
 
 def _orc_params(p):
     return oracle.make_params(a=p.a, gamma=p.gamma, kT=p.kT, dt=p.dt, mass=p.mass, body_f=p.body_f,
-                              flow_axis=p.flow_axis, grad_axis=p.grad_axis)
+                              flow_axis=p.flow_axis, grad_axis=p.grad_axis, kexp=p.kexp)
 
 
 def _force_check(f_gpu, f_orc, s_orc, label):
@@ -395,4 +395,46 @@ def test_empty_and_single_particle_boxes():
     b.step(3)
     f = b.read(dpd.FORCE)
     np.testing.assert_array_equal(f, [[-0.2, 0.0, 0.0]] if False else [[np.float32(-0.2), 0.0, 0.0]])
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# kernel exponent k (w_R = w^k, w_D = w_R^2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,cells,rho", [(0.25, (10, 9, 8), 4.0), (0.15, (7, 12, 9), 3.0), (0.5, (5, 5, 5), 8.0)])
+def test_kernel_exponent_forces(k, cells, rho):
+    pos, vel = inputs.uniform_state(cells, density=rho, seed=31)
+    p = dpd.make_params(a=18.75, gamma=4.5, kT=1.0, dt=0.005, kexp=k)
+    b = _box(cells, pos, vel, p, 31)
+    b.step(1)
+    f = b.read(dpd.FORCE)
+    b.close()
+    ids = np.arange(len(pos), dtype=np.uint32)
+    fo, so, _ = oracle.forces(pos, vel, ids, cells, _orc_params(p), 0, 31)
+    _force_check(f, fo, so, f"k={k}")
+    # the reference gather kernel gives the same bits as the tile kernel
+    pr = dpd.make_params(a=18.75, gamma=4.5, kT=1.0, dt=0.005, kexp=k, flags=dpd.FLAG_REFERENCE_FORCE)
+    br = _box(cells, pos, vel, pr, 31)
+    br.step(1)
+    np.testing.assert_array_equal(br.read(dpd.FORCE), f)
+    br.close()
+
+
+def test_kernel_exponent_one_and_zero_are_linear():
+    cells = (9, 8, 7)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=32)
+    out = []
+    for k in (1.0, 0.0):
+        b = _box(cells, pos, vel, dpd.make_params(kexp=k), 32)
+        b.step(3)
+        out.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE)))
+        b.close()
+    for x, y in zip(*out):
+        np.testing.assert_array_equal(x, y)
+    b = dpd.Box(cells, len(pos), seed=1)
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(dpd.DPDError) as e:
+            b.set_params(dpd.make_params(kexp=bad))
+        assert e.value.code == dpd.EINVAL
     b.close()

@@ -9,7 +9,11 @@
     force alone, checked against a potential computed here independently;
   - periodic Poiseuille flow (Sec. 4.2, Eq. 11): antisymmetric two-half
     parabola, with the viscosity of the Groot-Warren fluid of Table 1
-    (a = 25, gamma = 6.75, rho = 3, kT = 1, dt = 0.04: eta = 0.91).
+    (a = 25, gamma = 6.75, rho = 3, kT = 1, dt = 0.04: eta = 0.91);
+  - kernel exponent k (w_R = w^k, w_D = w_R^2, Sec. 2.1): the equilibrium
+    temperature stays kT at k = 1/4 (the fluctuation-dissipation pairing of
+    the two kernels), and the pressure's mean-field limit stays pi / 30
+    (k leaves the conservative weight alone).
 """
 import math
 
@@ -75,6 +79,31 @@ def test_pressure_mean_field_limit():
     """For a -> 0 the pair distribution tends to 1 and the virial gives
     alpha = (2 pi / 3) int_0^1 r^3 (1 - r) dr = pi / 30 exactly."""
     alpha = _eos_alpha((6, 6, 6), 3.0, 0.25, seed=22)
+    assert abs(alpha - math.pi / 30.0) < 0.04 * math.pi / 30.0, alpha
+
+
+def test_equilibrium_kT_kernel_exponent():
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, kT=1.0, seed=14)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, kexp=0.25)
+    diag, _, _, _ = oracle.step(x, v, ids, cells, p, seed=14, step0=0, nsteps=6000)
+    kt = diag["kT_centred"][1000:]
+    m, se = kt.mean(), _block_se(kt)
+    assert abs(m - 1.0) < 0.01, (m, se)
+
+
+def test_pressure_mean_field_limit_kernel_exponent():
+    pos, vel = inputs.uniform_state((6, 6, 6), density=3.0, kT=1.0, seed=23)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    a, rho = 0.25, 3.0
+    p = oracle.make_params(a=a, gamma=4.5, kT=1.0, dt=0.01, kexp=0.25)
+    diag, _, _, _ = oracle.step(x, v, ids, (6, 6, 6), p, 23, 0, 3000)
+    kt = diag["kT_centred"][500:].mean()
+    pr = diag["pressure"][500:].mean()
+    alpha = (pr - rho * kt) / (a * rho * rho)
     assert abs(alpha - math.pi / 30.0) < 0.04 * math.pi / 30.0, alpha
 
 

@@ -324,3 +324,32 @@ def test_diagnostics_momentum_balance():
     assert np.all(np.abs(dP[:, 1:]) < 1e-10)                       # no net force off the flow axis
     assert np.all(np.abs(dP[:, 0]) <= 0.1 * 0.01 * len(x) + 1e-10)
     assert np.all(np.abs(dP[:, 0] / (0.1 * 0.01) - np.rint(dP[:, 0] / (0.1 * 0.01))) < 1e-6)
+
+
+def test_kernel_exponent_one_is_the_linear_kernel():
+    """k = 1 (and 0, which selects it) give the linear kernel bit for bit."""
+    rng = np.random.default_rng(7)
+    box = np.array([6.0, 7.0, 8.0])
+    nhit = 0
+    for _ in range(50):
+        ri = rng.uniform(0, 6, 3)
+        rj = ri + rng.normal(0, 0.3, 3)
+        vi, vj = rng.normal(0, 1, 3), rng.normal(0, 1, 3)
+        outs = [oracle.pair_force(ri, rj, vi, vj, box, oracle.make_params(gamma=4.5, kT=1.0, kexp=k), 3, 9, 11, 5)
+                for k in (1.0, 0.0)]
+        assert outs[0][0] == outs[1][0]
+        nhit += outs[0][0]
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    assert nhit > 20
+
+
+def test_kernel_exponent_leaves_conservative_part():
+    """w^k enters only the random and dissipative terms: with gamma = 0 and
+    kT = 0 the force is a (1 - r) e for every k."""
+    box = np.array([5.0, 5.0, 5.0])
+    ri, rj = np.array([1.0, 1.0, 1.0]), np.array([1.3, 1.4, 1.2])
+    r = float(np.linalg.norm(ri - rj))
+    for k in (0.15, 0.25, 1.0):
+        F = oracle.pair_force(ri, rj, np.zeros(3), np.zeros(3), box,
+                              oracle.make_params(a=25.0, gamma=0.0, kT=0.0, kexp=k), 1, 2, 0, 0)[1]
+        np.testing.assert_allclose(F, 25.0 * (1.0 - r) * (ri - rj) / r, rtol=1e-14)
