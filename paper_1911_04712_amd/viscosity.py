@@ -24,8 +24,9 @@ import numpy as np
 
 from . import dpd
 
-# Table 1 rows with r_c = 1: DPD parameters, the paper's measured range and
-# the literature value it compares with.
+# Table 1: DPD parameters, the paper's measured range and the literature
+# value it compares with.  TABLE1_RC1 holds the r_c = 1 rows; the two
+# r_c = 1.5 rows follow in TABLE1.
 TABLE1_RC1 = [
     dict(a=0.9375, gamma=115.6, rho=4, k=1.0, kT=0.05, dt=0.01, eta_paper=(4.4, 4.6), eta_ref=4.7),
     dict(a=6.0, gamma=20.0, rho=3, k=0.15, kT=0.1, dt=0.002, eta_paper=(8.0, 8.3), eta_ref=8.1),
@@ -34,6 +35,19 @@ TABLE1_RC1 = [
     dict(a=18.75, gamma=4.5, rho=4, k=0.25, kT=1.0, dt=0.005, eta_paper=(2.44, 2.45), eta_ref=2.59),
     dict(a=0.0, gamma=20.25, rho=6, k=1.0, kT=0.5, dt=0.01, eta_paper=(2.08, 2.1), eta_ref=2.09),
 ]
+TABLE1 = TABLE1_RC1 + [
+    dict(a=4.0, gamma=8.0, rho=3, k=0.15, kT=0.1, dt=0.001, rc=1.5, eta_paper=(24.7, 26.3), eta_ref=26.3),
+    dict(a=4.0, gamma=40.0, rho=3, k=0.15, kT=0.1, dt=0.0002, rc=1.5, eta_paper=(122.5, 129.5), eta_ref=126.0),
+]
+
+
+def unit_cutoff(a, gamma, rho, kT, f, rc):
+    """The same fluid with r_c as the length unit (an exact change of units;
+    time and mass are kept): lengths and velocities scale by 1/r_c, forces
+    by 1/r_c, so a' = a / r_c, gamma' = gamma, sigma' = sigma / r_c
+    (kT' = kT / r_c^2), number density rho' = rho r_c^3, body force
+    f' = f / r_c; a viscosity measured in these units is eta' = eta r_c."""
+    return a / rc, gamma, rho * rc ** 3, kT / rc ** 2, f / rc
 
 
 def _shape(nb, L):
@@ -62,7 +76,7 @@ def fit_eta(profiles, rho, f, L):
 
 
 def measure(a, gamma, rho, k, kT, dt, eta_guess, f=None, cells=(16, 16, 16), warm_tau=10.0, blocks=10,
-            block_tau=3.0, seed=1):
+            block_tau=3.0, seed=1, rc=1.0):
     """Periodic-Poiseuille viscosity on the GPU.  Flow along x, gradient along
     y (cells[1] slabs of one cell).  The expected viscosity eta_guess sets
     only the drive and the run length: f gives a peak flow of about
@@ -70,7 +84,15 @@ def measure(a, gamma, rho, k, kT, dt, eta_guess, f=None, cells=(16, 16, 16), war
     warm_tau and block_tau momentum relaxation times rho (L/2)^2 / (pi^2 eta).
     eta_err is the block-scatter error of one run; slow flow fluctuations
     make runs with other seeds scatter about three times more, so main()
-    reports the scatter over seeds."""
+    reports the scatter over seeds.  A cutoff rc != 1 is run in units of
+    rc (unit_cutoff): cells are then cells of edge rc, and eta, eta_err and
+    f are returned in the original units."""
+    if rc != 1.0:
+        a1, g1, rho1, kT1, _ = unit_cutoff(a, gamma, rho, kT, 0.0, rc)
+        r = measure(a1, g1, rho1, k, kT1, dt, eta_guess * rc, None if f is None else f / rc, cells, warm_tau,
+                    blocks, block_tau, seed)
+        r.update(eta=r["eta"] / rc, eta_err=r["eta_err"] / rc, f=r["f"] * rc, kT_centred=r["kT_centred"] * rc * rc)
+        return r
     L = float(cells[1])
     n = int(round(rho * cells[0] * cells[1] * cells[2]))
     tau = rho * (L / 2) ** 2 / (math.pi ** 2 * eta_guess)
@@ -102,8 +124,9 @@ def measure(a, gamma, rho, k, kT, dt, eta_guess, f=None, cells=(16, 16, 16), war
 
 def main(argv=None):
     seeds = range(1, 5)
-    for row in TABLE1_RC1:
+    for row in TABLE1:
         par = {k: row[k] for k in ("a", "gamma", "rho", "k", "kT", "dt")}
+        par["rc"] = row.get("rc", 1.0)
         runs = [measure(**par, eta_guess=sum(row["eta_paper"]) / 2, seed=s) for s in seeds]
         etas = np.array([r["eta"] for r in runs])
         print(json.dumps({"params": par, "eta": float(etas.mean()),
