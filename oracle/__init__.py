@@ -17,7 +17,10 @@ _lib = None
 class Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
-                ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32), ("kexp", ctypes.c_double)]
+                ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32), ("kexp", ctypes.c_double),
+                ("ntypes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("type", ctypes.POINTER(ctypes.c_int32)), ("a_tab", ctypes.POINTER(ctypes.c_double)),
+                ("g_tab", ctypes.POINTER(ctypes.c_double))]
 
 
 class Diag(ctypes.Structure):
@@ -68,6 +71,22 @@ def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_a
     """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1)."""
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f),
                   int(flow_axis), int(grad_axis), float(kexp))
+
+
+def with_species(params, types, a_tab, g_tab):
+    """Copy of params for a mixture: types[i] is the species of row i of the
+    state, a_tab / g_tab the symmetric ntypes x ntypes tables of a and gamma
+    per species pair.  The arrays are kept alive by the returned object."""
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    a = np.ascontiguousarray(a_tab, dtype=np.float64)
+    g = np.ascontiguousarray(g_tab, dtype=np.float64)
+    nt = a.shape[0]
+    assert a.shape == (nt, nt) and g.shape == (nt, nt)
+    q = Params()
+    ctypes.pointer(q)[0] = params
+    q.ntypes, q.type, q.a_tab, q.g_tab = nt, _p(t, ctypes.c_int32), _p(a, ctypes.c_double), _p(g, ctypes.c_double)
+    q._keep = (t, a, g)
+    return q
 
 
 def philox4x32_10(ctr, key):

@@ -17,6 +17,9 @@
  *   - cell lists (edge r_c, sort by cell)  Sec. 3.2
  *   - fused velocity-Verlet (kick, drift)  Sec. 3.1, time-stepping step 5
  *   - periodic Poiseuille body force ..... Sec. 4.2, Eq. (11)
+ *   - several species with their own a and gamma per pair of species
+ *     (fluids of different viscosity side by side: Sec. 2.3, Sec. 5.2,
+ *     Sec. 5.3); kT, dt, the mass and the kernels stay shared
  *   - random term: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
  *     random numbers: as easy as 1, 2, 3", SC'11) followed by the
  *     Box-Muller transform (Box & Muller 1958).  The paper names no
@@ -50,6 +53,11 @@ typedef struct {
     int32_t grad_axis; /* axis whose coordinate selects the force sign     */
     double kexp;       /* kernel exponent k of w_R = w^k, 0 < k <= 1 (Sec. 2.1);
                           0 means k = 1                                   */
+    int32_t ntypes;    /* species; 0 or 1: one species with (a, gamma)     */
+    int32_t reserved;
+    const int32_t* type; /* species of each particle (row of x), ntypes > 1 */
+    const double* a_tab; /* ntypes x ntypes, symmetric: a of species pair  */
+    const double* g_tab; /* ntypes x ntypes, symmetric: gamma of the pair  */
 } orc_params;
 
 typedef struct {
@@ -271,6 +279,20 @@ static double orc_body_force(const double* r, const int32_t cells[3], const orc_
     return r[p->grad_axis] <= half ? -p->body_f : p->body_f;
 }
 
+/* Parameters of the pair of particles (rows) i and j: with several species
+ * the pair takes a and gamma of its species pair (s, t) from the symmetric
+ * tables, so F_ij = -F_ji still holds; everything else is shared. */
+static orc_params orc_pair_params(const orc_params* p, int64_t i, int64_t j)
+{
+    orc_params q = *p;
+    if (p->ntypes > 1) {
+        int64_t k = (int64_t)p->type[i] * p->ntypes + p->type[j];
+        q.a = p->a_tab[k];
+        q.gamma = p->g_tab[k];
+    }
+    return q;
+}
+
 /* Force on one particle i, gathering over its 27 neighbour cells (or over
  * all particles when brute != 0).  Writes f[3] (pair sum + body force),
  * *s (error scale) and adds i's half of the conservative virial. */
@@ -287,7 +309,8 @@ static void orc_force_on(int64_t i, int64_t n, const double* x, const double* v,
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             double F[3], Fc[3], mag;
-            if (orc_pair_force(ri, x + 3 * j, vi, v + 3 * j, box, p, id[i], id[j], step, seed, F, Fc,
+            orc_params q = orc_pair_params(p, i, j);
+            if (orc_pair_force(ri, x + 3 * j, vi, v + 3 * j, box, &q, id[i], id[j], step, seed, F, Fc,
                                &mag)) {
                 double d[3];
                 for (int k = 0; k < 3; ++k) {
@@ -313,7 +336,8 @@ static void orc_force_on(int64_t i, int64_t n, const double* x, const double* v,
                         int64_t j = order[k];
                         if (j == i) continue;
                         double F[3], Fc[3], mag;
-                        if (orc_pair_force(ri, x + 3 * j, vi, v + 3 * j, box, p, id[i], id[j], step,
+                        orc_params q = orc_pair_params(p, i, j);
+                        if (orc_pair_force(ri, x + 3 * j, vi, v + 3 * j, box, &q, id[i], id[j], step,
                                            seed, F, Fc, &mag)) {
                             double d[3];
                             for (int q = 0; q < 3; ++q) {
@@ -343,6 +367,25 @@ static int orc_check(const int32_t cells[3], const orc_params* p)
     if (!(p->kexp >= 0.0 && p->kexp <= 1.0)) return -1;
     if (p->flow_axis < 0 || p->flow_axis > 2 || p->grad_axis < 0 || p->grad_axis > 2) return -1;
     if (p->flow_axis == p->grad_axis) return -1;
+    if (p->ntypes < 0 || p->ntypes > 64) return -1;
+    if (p->ntypes > 1) {
+        if (!p->type || !p->a_tab || !p->g_tab) return -1;
+        for (int s = 0; s < p->ntypes; ++s)
+            for (int t = 0; t < p->ntypes; ++t) {
+                double a = p->a_tab[s * p->ntypes + t], g = p->g_tab[s * p->ntypes + t];
+                if (!isfinite(a) || !isfinite(g) || g < 0.0) return -1;
+                if (a != p->a_tab[t * p->ntypes + s] || g != p->g_tab[t * p->ntypes + s]) return -1;
+            }
+    }
+    return 0;
+}
+
+/* Every particle's species in [0, ntypes). */
+static int orc_check_types(int64_t n, const orc_params* p)
+{
+    if (p->ntypes <= 1) return 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (p->type[i] < 0 || p->type[i] >= p->ntypes) return -1;
     return 0;
 }
 
@@ -355,7 +398,7 @@ int orc_forces(int64_t n, const double* x, const double* v, const uint32_t* id,
                const int32_t cells[3], const orc_params* p, uint64_t step, uint64_t seed,
                int brute, int64_t m, const int64_t* which, double* f, double* s, double* virial)
 {
-    if (orc_check(cells, p)) return -1;
+    if (orc_check(cells, p) || orc_check_types(n, p)) return -1;
     double box[3] = {(double)cells[0], (double)cells[1], (double)cells[2]};
     int64_t nc = (int64_t)cells[0] * cells[1] * cells[2];
     int64_t* order = NULL;
@@ -403,7 +446,7 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
              const orc_params* p, uint64_t seed, uint64_t step0, int64_t nsteps, int32_t nbins,
              orc_diag* diag, double* prof_sum, double* prof_cnt, double* f_last)
 {
-    if (orc_check(cells, p)) return -1;
+    if (orc_check(cells, p) || orc_check_types(n, p)) return -1;
     if (n < 2 || nsteps < 0) return -1;
     double box[3] = {(double)cells[0], (double)cells[1], (double)cells[2]};
     double vol = box[0] * box[1] * box[2];

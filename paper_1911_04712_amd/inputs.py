@@ -92,6 +92,26 @@ def face_state(cells, n, kT=1.0, mass=1.0, seed=0, grid=None):
     return p.astype(np.float32), vel
 
 
+def species_types(n, fractions, seed=0):
+    """Species of n particles (id order), drawn independently with the given
+    probabilities (normalised), as int32."""
+    f = np.asarray(fractions, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed + 104729))
+    return rng.choice(len(f), size=int(n), p=f / f.sum()).astype(np.int32)
+
+
+# Two fluids of different viscosity in one domain (the plasma / cytoplasm
+# pair of Sec. 5.2-5.3, cytoplasm five times more viscous): the same
+# conservative a = 25 for every pair, gamma 4.5 within the solvent, 22.5
+# within the second fluid and 0 across, where only the conservative part
+# acts (the cross-membrane rule of Sec. 2.3).  Half the particles of each.
+MIXTURE_TABLES = {
+    "a": [[25.0, 25.0], [25.0, 25.0]],
+    "gamma": [[4.5, 0.0], [0.0, 22.5]],
+    "fractions": [0.5, 0.5],
+}
+
+
 # ---------------------------------------------------------------------------
 # The workloads (uniform DPD solvents; Sec. 5.1 uses L = 64, rho = 8 per GPU)
 # ---------------------------------------------------------------------------

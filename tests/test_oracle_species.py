@@ -1,0 +1,147 @@
+"""Pins of the oracle's species (per species-pair a and gamma).
+
+Several fluids share one domain with their own dissipative coefficient
+(Sec. 2.3, Sec. 5.2, Sec. 5.3: plasma and cytoplasm of different viscosity,
+and purely conservative coupling across a membrane).  What pins the oracle
+here, none of it a retyped formula of the oracle's own code:
+
+  - identical tables reduce to the single-species force bit for bit;
+  - the pair of species picks its own entry: a two-particle system gives
+    a_st (1 - r) and -gamma_st w^2 (e.v) for every (s, t) of a table whose
+    entries all differ;
+  - Newton's third law survives (symmetric tables): the pair forces of a
+    mixture sum to zero;
+  - equipartition: with gamma 4.5, 22.5 and 1 within and across species,
+    each species' own centred temperature is kT (fluctuation-dissipation
+    per pair: sigma_st^2 = 2 gamma_st kT);
+  - the mean-field (weak a) pressure of a mixture is
+    rho kT + (pi / 30) sum_st rho_s rho_t a_st;
+  - invalid tables and species are rejected.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_04712_amd import inputs
+
+
+def _state(cells, rho, seed, kT=1.0):
+    pos, vel = inputs.uniform_state(cells, density=rho, kT=kT, seed=seed)
+    return pos.astype(np.float64), vel.astype(np.float64), np.arange(len(pos), dtype=np.uint32)
+
+
+def test_identical_tables_equal_single_species():
+    cells = (6, 6, 6)
+    x, v, ids = _state(cells, 3.0, 31)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    types = inputs.species_types(len(x), [0.2, 0.3, 0.5], seed=31)
+    q = oracle.with_species(p, types, np.full((3, 3), 25.0), np.full((3, 3), 4.5))
+    for brute in (False, True):
+        f0, _, vir0 = oracle.forces(x, v, ids, cells, p, 5, 7, brute=brute)
+        f1, _, vir1 = oracle.forces(x, v, ids, cells, q, 5, 7, brute=brute)
+        assert np.array_equal(f0, f1)
+        assert vir1 == pytest.approx(vir0, rel=1e-12)      # threaded sum: order varies
+
+
+@pytest.mark.parametrize("s,t", [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (2, 1), (2, 2)])
+def test_pair_takes_its_species_entry(s, t):
+    a_tab = np.array([[10.0, 20.0, 30.0], [20.0, 40.0, 50.0], [30.0, 50.0, 70.0]])
+    g_tab = np.array([[1.0, 2.0, 3.0], [2.0, 5.0, 6.0], [3.0, 6.0, 9.0]])
+    cells = (4, 4, 4)
+    r = 0.625                                        # exact in binary
+    x = np.array([[1.5, 1.5, 1.5], [1.5 + r, 1.5, 1.5]])
+    ids = np.arange(2, dtype=np.uint32)
+    # conservative alone: no noise, no relative velocity
+    p = oracle.make_params(a=0.0, gamma=0.0, kT=0.0, dt=0.01)
+    q = oracle.with_species(p, [s, t], a_tab, g_tab)
+    f, _, _ = oracle.forces(x, np.zeros((2, 3)), ids, cells, q, 0, 0)
+    assert f[0, 0] == pytest.approx(-a_tab[s, t] * (1.0 - r), rel=1e-14)
+    assert f[1, 0] == pytest.approx(a_tab[s, t] * (1.0 - r), rel=1e-14)
+    # dissipative alone: a = 0 everywhere, kT = 0, particles approaching
+    q = oracle.with_species(p, [s, t], np.zeros((3, 3)), g_tab)
+    vel = np.array([[0.5, 0.0, 0.0], [-0.25, 0.0, 0.0]])
+    f, _, _ = oracle.forces(x, vel, ids, cells, q, 0, 0)
+    # e = (r_0 - r_1) / r = -x_hat, e.(v_0 - v_1) = -0.75: a repulsion of
+    # gamma (1 - r)^2 0.75 pushing 0 back along -x
+    assert f[0, 0] == pytest.approx(-g_tab[s, t] * (1.0 - r) ** 2 * 0.75, rel=1e-14)
+    assert f[1, 0] == pytest.approx(g_tab[s, t] * (1.0 - r) ** 2 * 0.75, rel=1e-14)
+
+
+def test_mixture_conserves_momentum():
+    cells = (6, 5, 7)
+    x, v, ids = _state(cells, 4.0, 32)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    types = inputs.species_types(len(x), [0.5, 0.25, 0.25], seed=32)
+    a_tab = np.array([[25.0, 18.0, 40.0], [18.0, 12.0, 30.0], [40.0, 30.0, 25.0]])
+    g_tab = np.array([[4.5, 0.0, 9.0], [0.0, 22.5, 3.0], [9.0, 3.0, 1.0]])
+    f, s, _ = oracle.forces(x, v, ids, cells, oracle.with_species(p, types, a_tab, g_tab), 3, 11)
+    assert np.all(np.abs(f.sum(axis=0)) < 1e-12 * s.sum())
+
+
+def _species_kT(x, v, ids, cells, q, types, seed, nsteps, every, skip):
+    """Time-centred temperature of each species, v^{n-1/2} + dt f^n / (2m)
+    = v^{n+1/2} - dt f^n / (2m), sampled every `every` steps."""
+    nt = int(types.max()) + 1
+    samples, step0 = [], 0
+    while step0 < nsteps:
+        _, _, _, fl = oracle.step(x, v, ids, cells, q, seed, step0, every, want_diag=False)
+        step0 += every
+        if step0 <= skip:
+            continue
+        vc = v - 0.5 * q.dt * fl / q.mass
+        ke = 0.5 * q.mass * (vc * vc).sum(axis=1)
+        samples.append([2.0 * ke[types == s].sum() / (3.0 * (types == s).sum()) for s in range(nt)])
+    return np.array(samples)
+
+
+@pytest.mark.slow
+def test_equipartition_across_species():
+    cells = (8, 8, 8)
+    x, v, ids = _state(cells, 3.0, 33)
+    types = inputs.species_types(len(x), [0.5, 0.5], seed=33)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    q = oracle.with_species(p, types, [[25.0, 25.0], [25.0, 25.0]], [[4.5, 1.0], [1.0, 22.5]])
+    kt = _species_kT(x, v, ids, cells, q, types, 33, 5000, 5, 1000)
+    m = kt.mean(axis=0)
+    # the centred estimator carries an O(dt^2 gamma) bias; 1.5 % covers it
+    # at gamma = 22.5, while a sigma that ignored the pair's gamma would put
+    # the two species a factor of about 5 apart
+    assert np.all(np.abs(m - 1.0) < 0.015), m
+
+
+@pytest.mark.slow
+def test_mixture_mean_field_pressure():
+    cells = (6, 6, 6)
+    x, v, ids = _state(cells, 3.0, 34)
+    types = inputs.species_types(len(x), [1.0 / 3.0, 2.0 / 3.0], seed=34)
+    a_tab = np.array([[0.3, 0.05], [0.05, 0.1]])
+    p = oracle.make_params(a=0.0, gamma=4.5, kT=1.0, dt=0.01)
+    q = oracle.with_species(p, types, a_tab, np.full((2, 2), 4.5))
+    diag, _, _, _ = oracle.step(x, v, ids, cells, q, 34, 0, 3000)
+    vol = float(np.prod(cells))
+    rho_s = np.array([(types == s).sum() for s in range(2)]) / vol
+    kt = diag["kT_centred"][500:].mean()
+    pex = diag["pressure"][500:].mean() - rho_s.sum() * kt
+    mean_field = math.pi / 30.0 * float(rho_s @ a_tab @ rho_s)
+    assert abs(pex - mean_field) < 0.04 * mean_field, (pex, mean_field)
+
+
+def test_invalid_species_rejected():
+    cells = (4, 4, 4)
+    x, v, ids = _state(cells, 3.0, 35)
+    p = oracle.make_params()
+    t = inputs.species_types(len(x), [0.5, 0.5], seed=35)
+    ok_a, ok_g = np.full((2, 2), 25.0), np.full((2, 2), 4.5)
+    oracle.forces(x, v, ids, cells, oracle.with_species(p, t, ok_a, ok_g), 0, 0)
+    bad = [
+        (t, [[25.0, 20.0], [21.0, 25.0]], ok_g),         # asymmetric a
+        (t, ok_a, [[4.5, -1.0], [-1.0, 4.5]]),           # negative gamma
+        (t, ok_a, [[4.5, np.nan], [np.nan, 4.5]]),        # non-finite
+        (np.where(t == 1, 2, t), ok_a, ok_g),            # species out of range
+        (np.where(t == 1, -1, t), ok_a, ok_g),
+    ]
+    for tt, a_tab, g_tab in bad:
+        with pytest.raises(RuntimeError):
+            oracle.forces(x, v, ids, cells, oracle.with_species(p, tt, a_tab, g_tab), 0, 0)
