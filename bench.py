@@ -152,6 +152,58 @@ def bench_batched(nboxes=64, steps=500, tune=True):
             "batch_tile": list(btile) if btile else "per-box", "batched_equals_plain": same}
 
 
+def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
+    """The same box as two fluids of different viscosity (half the particles
+    each, gamma 4.5 / 22.5 within and 0 across): throughput, force-kernel
+    time against the single-species kernel's roofline, and a sampled one-step
+    force check against the FP64 oracle."""
+    import numpy as np
+    import torch
+    from paper_1911_04712_amd import dpd, inputs
+    t = inputs.MIXTURE_TABLES
+    n = w.n
+    rho = n / float(w.cells[0] * w.cells[1] * w.cells[2])
+    pos, vel = inputs.uniform_state(w.cells, n=n, kT=w.kT, seed=w.seed)
+    types = inputs.species_types(n, t["fractions"], seed=w.seed)
+    params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass)
+    box = dpd.Box(w.cells, n, params=params, seed=w.seed)
+    box.set_state(pos, vel)
+    box.set_species(t["a"], t["gamma"])
+    box.set_types(types)
+    tile = list(box.tune_tile(reps=5)[0])
+    box.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    box.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = box.stats()
+    stage = box.profile_steps(50)
+    ach = force_ops(n, rho) / (stage["force"] / 1e3) / 1e12
+    out = {"workload": f"{w.name} as two species (a = 25; gamma 4.5, 22.5 within, 0 across; half each)",
+           "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "steps": steps, "tile": tile,
+           "ms_per_step": ms / steps, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "force_frac_of_alu_peak": round(ach / VALU_PEAK_TOPS, 4),
+           "kT_centred_last": st["kT_centred"], "nonfinite": st["nonfinite"]}
+    if check:
+        import oracle
+        pe, ve = box.read(dpd.POS), box.read(dpd.VEL)
+        box.set_state(pe, ve)
+        box.set_types(types)
+        box.step(1)
+        fg = box.read(dpd.FORCE).astype(np.float64)
+        which = np.random.Generator(np.random.PCG64(7)).choice(n, size=min(sample, n), replace=False)
+        op = oracle.with_species(oracle.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass),
+                                 types, t["a"], t["gamma"])
+        fo, so, _ = oracle.forces(pe, ve, np.arange(n, dtype=np.uint32), w.cells, op, 0, w.seed, which=which)
+        out["force_max_err_over_scale"] = float(np.max(np.linalg.norm(fg[which] - fo, axis=1) / so))
+        out["force_check_sample"] = int(len(which))
+    box.close()
+    return out
+
+
 def bench_served(nreq=1000, quantum=50, pool_gb=32, max_slots=256):
     """Poisson trace of requests (mean 200/s, edges log-uniform [8, 48], rho 3
     or 8, 500 steps): continuous batching vs FIFO one request at a time."""
@@ -223,12 +275,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cube48_rho3")
     ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage with HIP events")
-    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps in the CPU baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default cell tile of the force kernel")
     ap.add_argument("--tile", default="", help="cell tile of the force kernel, e.g. 6,3,3 (no autotuning)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-species", action="store_true", help="skip the two-species measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device copy of this many MiB (reference for HBM counters)")
@@ -331,6 +384,8 @@ def main():
                                "sample": f"{sample_steps} steps of the same {w.name} box ({n} particles), "
                                          f"{cs:.1f} s"}
     box.close()
+    if not args.no_species:
+        out["species"] = bench_species(w, check=not args.no_cpu_baseline)
     if not args.no_batched:
         out["batched"] = bench_batched()
     if not args.no_served:

@@ -69,6 +69,9 @@ enum {
 
 enum { DPD_HOST = 0, DPD_DEVICE = 1 };
 
+/* most species of one box (dpd_set_species) */
+enum { DPD_MAX_TYPES = 8 };
+
 /* quantities for dpd_read */
 enum {
     DPD_POS = 0,          /* x^n (after the last step), wrapped into [0, L)           */
@@ -151,6 +154,33 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
 
 /* Set model parameters; validated as documented at dpd_params. */
 int dpd_set_params(dpd_box box, const dpd_params* params);
+
+/* Species: several fluids in one box, each pair of species with its own
+ * conservative amplitude and dissipative coefficient (fluids of different
+ * viscosity side by side, Sec. 2.3, Sec. 5.2 and Sec. 5.3 of the paper; a
+ * cross entry gamma = 0 couples two fluids through the conservative force
+ * alone).  a_tab and gamma_tab are host arrays of ntypes x ntypes doubles,
+ * row-major, symmetric, finite, gamma >= 0; the pair (s, t) then takes
+ * a = a_tab[s][t], gamma = gamma_tab[s][t] and sigma = sqrt(2 gamma kT),
+ * and dpd_params.a / .gamma are ignored.  kT, dt, the mass and the kernels
+ * stay shared.  ntypes in 1..DPD_MAX_TYPES; ntypes = 0 returns to one
+ * species described by dpd_params.  DPD_EINVAL if a particle already has a
+ * species >= ntypes.  The tables are copied; may be called at any time
+ * (also between steps) and take effect from the next step. */
+int dpd_set_species(dpd_box box, int32_t ntypes, const double* a_tab, const double* gamma_tab);
+
+/* Number of species set by dpd_set_species (0: one species from params). */
+int dpd_get_species(dpd_box box, int32_t* ntypes);
+
+/* Species of each particle: type_host[i] (host array of n int32) is the
+ * species of particle id i, each in 0..ntypes-1 (DPD_EINVAL otherwise,
+ * DPD_ESTATE before dpd_set_species or without a state).  dpd_set_state and
+ * dpd_init_random make every particle species 0.  Synchronises. */
+int dpd_set_types(dpd_box box, const int32_t* type_host);
+
+/* Read the species back, row i = particle id i (host array of n int32).
+ * Synchronises. */
+int dpd_get_types(dpd_box box, int32_t* type_host);
 
 /* Cell-tile shape of the LDS pair-force kernel: tile[3] edges in cells
  * (each 1..16), or {0, 0, 0} for the default chosen from the density.

@@ -64,7 +64,7 @@ double grid_of(const dpd_geom* g)
 constexpr int kGraphSteps = 8;          // steps per captured graph of a single box
 constexpr int kBatchGraphMax = 1024;    // a batch run of up to this many steps is one graph launch
 constexpr int kBatchGraphMin = 64;      // shorter batch runs are launched directly (no capture)
-constexpr size_t kLdsLimit = 160 * 1024 - 256;   // LDS per CU less the kernels' static LDS
+constexpr size_t kLdsLimit = 160 * 1024 - 1280;  // LDS per CU less the kernels' static LDS
 
 // Tile shapes the autotuners try (cells per edge).
 constexpr int kTuneCand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 4, 2}, {6, 3, 3}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4},
@@ -139,6 +139,12 @@ struct dpd_box_s {
 
     int tile_req[3] = {0, 0, 0};
 
+    // species: ntypes = 0 uses params.a / params.gamma for every pair
+    int ntypes = 0;
+    double a_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
+    double g_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
+    int max_type = 0;          // largest species assigned since the state was loaded
+
     // captured multi-step graph
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -164,11 +170,28 @@ dpd::ForceConst force_const(const dpd_box_s* b)
 {
     dpd::ForceConst fc{};
     const dpd_params& p = b->params;
-    fc.pc.a = (float)p.a;
-    fc.pc.gamma = (float)p.gamma;
-    fc.pc.sig_rdt = (float)(std::sqrt(2.0 * p.gamma * p.kT) / std::sqrt(p.dt));
+    auto sig_rdt = [&](double g) { return (float)(std::sqrt(2.0 * g * p.kT) / std::sqrt(p.dt)); };
     fc.pc.k0 = (uint32_t)b->seed;
     fc.pc.k1 = (uint32_t)(b->seed >> 32);
+    fc.ntypes = b->ntypes;
+    if (b->ntypes >= 1) {
+        constexpr int M = dpd::kMaxTypes;
+        for (int u = 0; u < b->ntypes; ++u)
+            for (int v = 0; v < b->ntypes; ++v) {
+                const double a = b->a_tab[u * M + v], g = b->g_tab[u * M + v];
+                fc.tab[u * M + v] = make_float4((float)a, (float)g, sig_rdt(g), 0.0f);
+            }
+        fc.pc.a = fc.tab[0].x;         // one species: the table's only entry, on the plain path
+        fc.pc.gamma = fc.tab[0].y;
+        fc.pc.sig_rdt = fc.tab[0].z;
+    } else {
+        fc.pc.a = (float)p.a;
+        fc.pc.gamma = (float)p.gamma;
+        fc.pc.sig_rdt = sig_rdt(p.gamma);
+    }
+    if (b->ntypes <= 1)                // every entry is the one species (a batch may run this box on
+        for (auto& e : fc.tab)         // the species kernel, whatever its particles' .w hold)
+            e = make_float4(fc.pc.a, fc.pc.gamma, fc.pc.sig_rdt, 0.0f);
     fc.pc.kgen = (p.kexp != 0.0 && p.kexp != 1.0) ? 1 : 0;
     fc.pc.kexp = fc.pc.kgen ? (float)p.kexp : 1.0f;
     for (int k = 0; k < 3; ++k) {
@@ -265,6 +288,7 @@ int push_desc(dpd_box_s* b)
     b->lp.lds_force = d.tc.lds_bytes;
     b->lp.any_virial = (d.flags & DPD_FLAG_VIRIAL) != 0;
     b->lp.reference_force = (d.flags & DPD_FLAG_REFERENCE_FORCE) != 0;
+    b->lp.species = d.fc.ntypes > 1;
     HIPCHK(dpd::force_tiled_prepare(d.tc.lds_bytes));
     HIPCHK(hipMemcpyAsync(b->d_desc, &d, sizeof d, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_pre, pre, sizeof pre, hipMemcpyHostToDevice, b->stream));
@@ -412,6 +436,76 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
     return push_desc(b);
 }
 
+int dpd_set_species(dpd_box b, int32_t ntypes, const double* a_tab, const double* gamma_tab)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_set_species: null box");
+    if (ntypes < 0 || ntypes > dpd::kMaxTypes) return fail(DPD_EINVAL, "dpd_set_species: ntypes must be in 0..%d", dpd::kMaxTypes);
+    if (ntypes > 0 && (!a_tab || !gamma_tab)) return fail(DPD_EINVAL, "dpd_set_species: null table");
+    if (ntypes > 0 && b->max_type >= ntypes)
+        return fail(DPD_EINVAL, "dpd_set_species: particles of species %d exist; need ntypes > %d", b->max_type, b->max_type);
+    for (int u = 0; u < ntypes; ++u)
+        for (int v = 0; v < ntypes; ++v) {
+            const double a = a_tab[u * ntypes + v], g = gamma_tab[u * ntypes + v];
+            if (!std::isfinite(a) || !std::isfinite(g) || g < 0.0 || std::fabs(a) > 1e8 || g > 1e8)
+                return fail(DPD_EINVAL, "dpd_set_species: entry (%d, %d) not finite, gamma < 0 or out of range", u, v);
+            if (a != a_tab[v * ntypes + u] || g != gamma_tab[v * ntypes + u])
+                return fail(DPD_EINVAL, "dpd_set_species: tables must be symmetric (entry (%d, %d))", u, v);
+        }
+    constexpr int M = dpd::kMaxTypes;
+    for (int k = 0; k < M * M; ++k) b->a_tab[k] = b->g_tab[k] = 0.0;
+    for (int u = 0; u < ntypes; ++u)
+        for (int v = 0; v < ntypes; ++v) {
+            b->a_tab[u * M + v] = a_tab[u * ntypes + v];
+            b->g_tab[u * M + v] = gamma_tab[u * ntypes + v];
+        }
+    if ((b->ntypes > 1) != (ntypes > 1)) b->graph_dirty = true;   // another force kernel
+    b->ntypes = ntypes;
+    return push_desc(b);
+}
+
+int dpd_get_species(dpd_box b, int32_t* ntypes)
+{
+    if (!b || !ntypes) return fail(DPD_EINVAL, "dpd_get_species: null argument");
+    *ntypes = b->ntypes;
+    return DPD_OK;
+}
+
+int dpd_set_types(dpd_box b, const int32_t* type_host)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_set_types: null box");
+    if (!b->have_state) return fail(DPD_ESTATE, "dpd_set_types: no state loaded");
+    if (b->ntypes < 1) return fail(DPD_ESTATE, "dpd_set_types: set the species tables first");
+    if (b->n > 0 && !type_host) return fail(DPD_EINVAL, "dpd_set_types: null array");
+    int mx = 0;
+    for (int i = 0; i < b->n; ++i) {
+        if (type_host[i] < 0 || type_host[i] >= b->ntypes)
+            return fail(DPD_EINVAL, "dpd_set_types: particle %d has species %d outside 0..%d", i, type_host[i], b->ntypes - 1);
+        mx = std::max(mx, (int)type_host[i]);
+    }
+    if (b->n == 0) return DPD_OK;
+    const dpd::BoxDesc& d = b->hd;
+    int* staged = (int*)b->out;
+    HIPCHK(hipMemcpyAsync(staged, type_host, (size_t)b->n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(dpd::launch_set_types(d.pos_a, d.vel_a, b->n, staged, b->stream));
+    if (b->binned || b->have_force)     // pos_b / vel_b hold a copy of the state in cell order
+        HIPCHK(dpd::launch_set_types(d.pos_b, d.vel_b, b->n, staged, b->stream));
+    b->max_type = mx;
+    return sync_box(b);
+}
+
+int dpd_get_types(dpd_box b, int32_t* type_host)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_get_types: null box");
+    if (!b->have_state) return fail(DPD_ESTATE, "dpd_get_types: no state loaded");
+    if (b->n > 0 && !type_host) return fail(DPD_EINVAL, "dpd_get_types: null array");
+    if (b->n == 0) return DPD_OK;
+    const dpd::BoxDesc& d = b->hd;
+    int* staged = (int*)b->out;
+    HIPCHK(dpd::launch_get_types(d.pos_a, d.vel_a, b->n, staged, b->stream));
+    HIPCHK(hipMemcpyAsync(type_host, staged, (size_t)b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    return sync_box(b);
+}
+
 int dpd_set_tile(dpd_box b, const int32_t tile[3])
 {
     if (!b || !tile) return fail(DPD_EINVAL, "dpd_set_tile: null argument");
@@ -447,6 +541,7 @@ int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where
     if (where != DPD_HOST && where != DPD_DEVICE) return fail(DPD_EINVAL, "dpd_set_state: bad `where`");
     if (b->n > 0 && (!pos_n3 || !vel_n3)) return fail(DPD_EINVAL, "dpd_set_state: null array");
     b->have_state = b->keys_valid = b->binned = b->have_force = false;
+    b->max_type = 0;                                   // every particle starts as species 0
     const dpd::BoxDesc& d = b->hd;
     const float *pp = pos_n3, *vp = vel_n3;
     const size_t bytes = (size_t)b->n * 3 * sizeof(float);
@@ -478,6 +573,7 @@ int dpd_init_random(dpd_box b, double kT, uint64_t seed)
     if (!b->have_params) return fail(DPD_ESTATE, "dpd_init_random: set params first (the mass scales velocities)");
     if (!std::isfinite(kT) || kT < 0.0) return fail(DPD_EINVAL, "dpd_init_random: kT must be finite and >= 0");
     b->have_state = b->keys_valid = b->binned = b->have_force = false;
+    b->max_type = 0;                                   // every particle starts as species 0
     const dpd::BoxDesc& d = b->hd;
     HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
     HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
@@ -758,15 +854,16 @@ int batch_refresh(dpd_batch_s* bt)
     std::vector<dpd::BoxDesc> h(nb);
     bt->pre.assign((size_t)dpd::kNumWork * (nb + 1), 0);
     int lds = 0;
-    bool virial = false;
+    bool virial = false, species = false;
     for (int i = 0; i < nb; ++i) {
         h[i] = bt->boxes[i]->hd;
         lds = std::max(lds, h[i].tc.lds_bytes);
         virial |= (h[i].flags & DPD_FLAG_VIRIAL) != 0;
+        species |= h[i].fc.ntypes > 1;
         for (int k = 0; k < dpd::kNumWork; ++k)
             bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
     }
-    bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial;
+    bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
         changed |= bt->lp.total[k] != tot;
@@ -777,6 +874,7 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.nbox = nb;
     bt->lp.lds_force = lds;
     bt->lp.any_virial = virial;
+    bt->lp.species = species;
     bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
     if (changed) bt->graph_steps = 0;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));

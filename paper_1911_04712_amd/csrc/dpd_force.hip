@@ -79,7 +79,9 @@ __device__ __forceinline__ bool pair_fx(float4 pi, float4 vi, float4 pj, float4 
     return true;
 }
 
-// Force on particle i (cell order) by gathering over its 27 neighbour cells.
+// Force on particle i (cell order) by gathering over its 27 neighbour cells;
+// kSp: each pair takes its species pair's entry of the table.
+template <bool kSp>
 __device__ float4 gather_force_one(int i, const float4* __restrict__ pos, const float4* __restrict__ vel,
                                    const int* __restrict__ cell_start, const ForceConst& fc, uint32_t step, bool& bad)
 {
@@ -110,7 +112,17 @@ __device__ float4 gather_force_one(int i, const float4* __restrict__ pos, const 
                     const float r2 = dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z);
                     if (!(r2 < 1.0f) || r2 == 0.0f) continue;
                     long long fx, fy, fz;
-                    bad |= !pair_fx(pi, vi, pj, vel[j], step, fc.pc, fx, fy, fz);
+                    const float4 vj = vel[j];
+                    if constexpr (kSp) {
+                        PairConst pc = fc.pc;
+                        const float4 c = fc.tab[species_pair(__float_as_int(vi.w), __float_as_int(vj.w))];
+                        pc.a = c.x;
+                        pc.gamma = c.y;
+                        pc.sig_rdt = c.z;
+                        bad |= !pair_fx(pi, vi, pj, vj, step, pc, fx, fy, fz);
+                    } else {
+                        bad |= !pair_fx(pi, vi, pj, vj, step, fc.pc, fx, fy, fz);
+                    }
                     ax += fx;
                     ay += fy;
                     az += fz;
@@ -130,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restri
     const int i = ((int)blockIdx.x - pre_[box]) * kBlock + threadIdx.x;
     if (i >= d.n) return;
     bool bad = false;
-    d.force[i] = gather_force_one(i, d.pos_b, d.vel_b, d.cell_start, d.fc, (uint32_t)d.st->step, bad);
+    const uint32_t step = (uint32_t)d.st->step;
+    d.force[i] = d.fc.ntypes > 1 ? gather_force_one<true>(i, d.pos_b, d.vel_b, d.cell_start, d.fc, step, bad)
+                                 : gather_force_one<false>(i, d.pos_b, d.vel_b, d.cell_start, d.fc, step, bad);
     if (bad) atomicOr(&d.st->nonfinite, 1);
 }
 
@@ -161,14 +175,31 @@ __device__ __forceinline__ int small_div(int x, float inv)
     return (int)(((float)x + 0.5f) * inv);
 }
 
+// Staged velocity .w: the tile index (-1 outside the tile); with species
+// (kSp) its low 24 bits hold the tile index and the top 8 bits the species.
+template <bool kSp>
 __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const float4* sv, long long* acc,
-                                          uint32_t step, const PairConst& pc, bool& bad)
+                                          uint32_t step, const PairConst& pc, const float4* tab, bool& bad)
 {
     const int a = (int)(e >> 16), b = (int)(e & 0xffffu);
     const float4 va = sv[a], vb = sv[b];
     long long fx, fy, fz;
-    bad |= !pair_fx(sp[a], va, sp[b], vb, step, pc, fx, fy, fz);
-    const int ia = __float_as_int(va.w), ib = __float_as_int(vb.w);
+    const int wa = __float_as_int(va.w), wb = __float_as_int(vb.w);
+    int ia, ib;
+    if constexpr (kSp) {
+        PairConst q = pc;
+        const float4 c = tab[species_pair((int)((unsigned)wa >> 24), (int)((unsigned)wb >> 24))];
+        q.a = c.x;
+        q.gamma = c.y;
+        q.sig_rdt = c.z;
+        bad |= !pair_fx(sp[a], va, sp[b], vb, step, q, fx, fy, fz);
+        ia = wa & 0xffffff;
+        ib = (wb << 8) >> 8;
+    } else {
+        bad |= !pair_fx(sp[a], va, sp[b], vb, step, pc, fx, fy, fz);
+        ia = wa;
+        ib = wb;
+    }
     atomicAdd((unsigned long long*)&acc[3 * ia], (unsigned long long)fx);
     atomicAdd((unsigned long long*)&acc[3 * ia + 1], (unsigned long long)fy);
     atomicAdd((unsigned long long*)&acc[3 * ia + 2], (unsigned long long)fz);
@@ -179,6 +210,7 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
     }
 }
 
+template <bool kSp>
 __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __restrict__ desc,
                                                              const int* __restrict__ pre, int nbox)
 {
@@ -194,13 +226,19 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
     int* __restrict__ nonfinite = &d.st->nonfinite;
     extern __shared__ __align__(16) unsigned char lds[];
     float4* sp = (float4*)lds;                                  // staged positions (image-shifted), w = id
-    float4* sv = (float4*)(lds + tc.off_sv);                    // staged velocities, w = tile index or -1
+    float4* sv = (float4*)(lds + tc.off_sv);                    // staged velocities, w = tile index or -1 (+ species)
     long long* acc = (long long*)(lds + tc.off_acc);            // fixed-point force of tile particles
     int* cst = (int*)(lds + tc.off_cst);                        // staged cell offsets in LDS (ncs + 1)
     int* cg = (int*)(lds + tc.off_cg);                          // staged cell start in HBM (cell order)
     int4* rows = (int4*)(lds + tc.off_rows);                    // tile rows: (lds start, len, HBM start, tile start)
     unsigned* qall = (unsigned*)(lds + tc.off_q);               // per-wave hit queues
     __shared__ int s_scr[kForceBlock / 64];
+    const float4* tab = nullptr;                                // species pair table (kSp)
+    if constexpr (kSp) {
+        __shared__ float4 s_tab[kMaxTypes * kMaxTypes];
+        for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += blockDim.x) s_tab[k] = fc.tab[k];
+        tab = s_tab;                                            // visible after the first barrier below
+    }
 
     // Consecutive tiles go to the same XCD (workgroups are dealt to the 8
     // XCDs round-robin and every box's range starts at a multiple of 8), so
@@ -264,7 +302,7 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
         for (int r = wave; r < nrows; r += nw) {
             const int4 rw = rows[r];
             for (int k = lane; k < rw.y; k += 64)
-                force[rw.z + k] = gather_force_one(rw.z + k, pos, vel, cell_start, fc, step, bad);
+                force[rw.z + k] = gather_force_one<kSp>(rw.z + k, pos, vel, cell_start, fc, step, bad);
         }
         if (bad) atomicOr(nonfinite, 1);
         return;
@@ -306,6 +344,10 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
             const float4 p0 = gload4(pos, src[0]), v0 = gload4(vel, src[0]);
             const float4 p1 = gload4(pos, src[1]), v1 = gload4(vel, src[1]);
             sp[s0] = make_float4(p0.x + shx[0], p0.y + shy[0], p0.z + shz[0], p0.w);
+            if constexpr (kSp) {
+                tiv[0] = (tiv[0] & 0xffffff) | (__float_as_int(v0.w) << 24);
+                tiv[1] = (tiv[1] & 0xffffff) | (__float_as_int(v1.w) << 24);
+            }
             sv[s0] = make_float4(v0.x, v0.y, v0.z, __int_as_float(tiv[0]));
             const int s1 = s0 + (int)blockDim.x;
             if (s1 < S) {
@@ -423,7 +465,7 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
                     __builtin_amdgcn_wave_barrier();
                     int fh = 0;
                     do {
-                        flush_hit(q[fh + lane], sp, sv, acc, step, fc.pc, bad);
+                        flush_hit<kSp>(q[fh + lane], sp, sv, acc, step, fc.pc, tab, bad);
                         fh += 64;
                     } while (qt - fh >= 64);
                     const unsigned rest = q[fh + lane];          // move what is left (< 64) to the front
@@ -436,7 +478,7 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < qt) flush_hit(q[lane], sp, sv, acc, step, fc.pc, bad);
+    if (lane < qt) flush_hit<kSp>(q[lane], sp, sv, acc, step, fc.pc, tab, bad);
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
 
@@ -494,17 +536,24 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
         if (lp.total[kWPart] > 0)
             hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
-        hipLaunchKernelGGL(k_force_tiled, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc, lp.pre,
-                           lp.nbox);
+        if (lp.species)
+            hipLaunchKernelGGL(k_force_tiled<true>, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc,
+                               lp.pre, lp.nbox);
+        else
+            hipLaunchKernelGGL(k_force_tiled<false>, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc,
+                               lp.pre, lp.nbox);
     }
     return hipGetLastError();
 }
 
 hipError_t force_tiled_prepare(int lds_bytes)
 {
-    if (lds_bytes > 65536)
-        return hipFuncSetAttribute((const void*)k_force_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    return hipSuccess;
+    if (lds_bytes <= 65536) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_force_tiled<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       lds_bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_force_tiled<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    return e;
 }
 
 }  // namespace dpd

@@ -16,6 +16,7 @@ constexpr int kProfileMaxBins = 4096;
 constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred
 constexpr int kFlagVirial = 1;          // DPD_FLAG_VIRIAL
 constexpr int kFlagReference = 2;       // DPD_FLAG_REFERENCE_FORCE
+constexpr int kMaxTypes = 8;            // species of one box (DPD_MAX_TYPES)
 
 // Fixed-point scale of the flow-profile and virial accumulators.
 constexpr double kProfScale = 16777216.0;      // 2^24 units per velocity unit
@@ -64,7 +65,13 @@ struct ForceConst {
     float body_f;
     int flow_axis, grad_axis;
     float half_grad;   // L_grad / 2
+    int ntypes;        // species; > 1: each pair takes (a, gamma, sigma / sqrt(dt)) from tab
+    float4 tab[kMaxTypes * kMaxTypes];   // [s * kMaxTypes + t], symmetric; unused entries 0
 };
+
+// Table entry of the species pair (s, t).  The species sit in the .w of the
+// velocity (an int); the masks keep any value inside the table.
+__device__ __forceinline__ int species_pair(int s, int t) { return ((s & (kMaxTypes - 1)) * kMaxTypes) | (t & (kMaxTypes - 1)); }
 
 // Tiling of the box for the LDS pair-force kernel, with the byte offsets of
 // its dynamic LDS buffers.
@@ -114,6 +121,7 @@ struct LaunchPlan {
     int nbox;
     int total[kNumWork];       // workgroups per kind
     int lds_force;             // dynamic LDS of the tile kernel (max over boxes)
+    bool species;              // some box has several species: the tile kernel reads the pair table
     bool any_virial;
     bool reference_force;      // single box flagged DPD_FLAG_REFERENCE_FORCE
 };
@@ -151,6 +159,9 @@ hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4
 hipError_t launch_init_random(int n, const float* L, float q, double vscale, uint64_t seed, float4* pos, float4* vel,
                               double* scratch, int scratch_doubles, hipStream_t s);
 hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s);
+// species by id -> vel[i].w of the particle whose id is pos[i].w, and back
+hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s);
+hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* type_by_id, hipStream_t s);
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_force(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);

@@ -207,6 +207,38 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
     return hipGetLastError();
 }
 
+// Species by particle id into the .w of the velocity row holding that id.
+__global__ void k_set_types(const float4* __restrict__ pos, float4* __restrict__ vel, int n,
+                            const int* __restrict__ type_by_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int id = __float_as_int(pos[i].w);
+    vel[i].w = __int_as_float(type_by_id[id]);
+}
+
+__global__ void k_get_types(const float4* __restrict__ pos, const float4* __restrict__ vel, int n,
+                            int* __restrict__ type_by_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    type_by_id[__float_as_int(pos[i].w)] = __float_as_int(vel[i].w);
+}
+
+hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_types, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, type_by_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* type_by_id, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_get_types, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, type_by_id);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // step kernels: each workgroup finds its box in the launch group, then works
 // on that box exactly as it would alone (same partition, same order)
@@ -345,11 +377,14 @@ __global__ __launch_bounds__(kBlock) void k_virial(const BoxDesc* __restrict__ d
     __shared__ long long scratch[kBlock / 64];
     const ForceConst& fc = d.fc;
     const float4* __restrict__ pos = d.pos_b;
+    const float4* __restrict__ vel = d.vel_b;
     const int* __restrict__ cell_start = d.cell_start;
     const int i = lb * kBlock + threadIdx.x;
+    const bool species = fc.ntypes > 1;
     double acc = 0.0;
     if (i < d.n) {
         const float4 pi = pos[i];
+        const int ti = species ? __float_as_int(vel[i].w) : 0;
         const int Lx = fc.cells[0], Ly = fc.cells[1], Lz = fc.cells[2];
         const int cx = cell_coord(pi.x, Lx), cy = cell_coord(pi.y, Ly), cz = cell_coord(pi.z, Lz);
         for (int dz = -1; dz <= 1; ++dz) {
@@ -374,7 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_virial(const BoxDesc* __restrict__ d
                         const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                         if (!(r2 < 1.0) || r2 == 0.0) continue;
                         const double r = sqrt(r2);
-                        acc += 0.5 * (double)fc.pc.a * (1.0 - r) * r;
+                        const float a = species ? fc.tab[species_pair(ti, __float_as_int(vel[j].w))].x : fc.pc.a;
+                        acc += 0.5 * (double)a * (1.0 - r) * r;
                     }
                 }
             }
@@ -458,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         const ArrivalTicket tk = arrival_issue(c, live, d.count);     // atomic in flight meanwhile
         if (live) {
             pos_a[i] = make_float4(nx, ny, nz, x.w);
-            vel_a[i] = make_float4(vx, vy, vz, 0.0f);
+            vel_a[i] = make_float4(vx, vy, vz, v.w);              // .w: species
         }
         if (live && fin) {
             m[0] += (double)vx;

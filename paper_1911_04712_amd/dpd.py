@@ -97,6 +97,10 @@ SIGNATURES = {
     "dpd_server_clock": ([_VP], ctypes.c_double),
     "dpd_server_destroy": ([_VP], ctypes.c_int),
     "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
+    "dpd_set_species": ([_VP, ctypes.c_int32, _VP, _VP], ctypes.c_int),
+    "dpd_get_species": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "dpd_set_types": ([_VP, _VP], ctypes.c_int),
+    "dpd_get_types": ([_VP, _VP], ctypes.c_int),
     "dpd_build_cells": ([_VP], ctypes.c_int),
     "dpd_step": ([_VP, _I64], ctypes.c_int),
     "dpd_read": ([_VP, ctypes.c_int, _VP, ctypes.c_int], ctypes.c_int),
@@ -243,6 +247,35 @@ class Box:
         if wp != wv:
             raise ValueError("pos and vel must both be host arrays or both device tensors")
         _check(lib().dpd_set_state(self._h, pp, vp, wp))
+
+    def set_species(self, a_tab=None, gamma_tab=None):
+        """Per species-pair a and gamma (symmetric ntypes x ntypes tables);
+        no tables returns to the single species of the params."""
+        if a_tab is None:
+            _check(lib().dpd_set_species(self._h, 0, None, None))
+            return
+        a = np.ascontiguousarray(a_tab, dtype=np.float64)
+        g = np.ascontiguousarray(gamma_tab, dtype=np.float64)
+        if a.ndim != 2 or a.shape[0] != a.shape[1] or g.shape != a.shape:
+            raise ValueError("a_tab and gamma_tab must be square tables of one shape")
+        _check(lib().dpd_set_species(self._h, a.shape[0], a.ctypes.data, g.ctypes.data))
+
+    def get_species(self):
+        nt = ctypes.c_int32()
+        _check(lib().dpd_get_species(self._h, ctypes.byref(nt)))
+        return nt.value
+
+    def set_types(self, types):
+        """Species of particle id i = types[i] (host array of n ints)."""
+        t = np.ascontiguousarray(types, dtype=np.int32)
+        if t.shape != (self.n,):
+            raise ValueError(f"types must have shape ({self.n},)")
+        _check(lib().dpd_set_types(self._h, t.ctypes.data))
+
+    def get_types(self):
+        t = np.empty(self.n, dtype=np.int32)
+        _check(lib().dpd_get_types(self._h, t.ctypes.data))
+        return t
 
     def init_random(self, kT, seed):
         """Random state generated on the device (uniform positions, Maxwellian
