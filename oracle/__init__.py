@@ -20,7 +20,9 @@ class Params(ctypes.Structure):
                 ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32), ("kexp", ctypes.c_double),
                 ("ntypes", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("type", ctypes.POINTER(ctypes.c_int32)), ("a_tab", ctypes.POINTER(ctypes.c_double)),
-                ("g_tab", ctypes.POINTER(ctypes.c_double))]
+                ("g_tab", ctypes.POINTER(ctypes.c_double)),
+                ("body_uniform", ctypes.c_int32), ("wall_kind", ctypes.c_int32), ("wall_h", ctypes.c_double),
+                ("frozen", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class Diag(ctypes.Structure):
@@ -61,6 +63,8 @@ def lib():
         L.orc_step.argtypes = [ctypes.c_int64, dp, dp, u32p, i32p, ctypes.POINTER(Params),
                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                                ctypes.POINTER(Diag), dp, dp, dp]
+        L.orc_sdf.argtypes = [dp, i32p, ctypes.POINTER(Params)]
+        L.orc_sdf.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -87,6 +91,32 @@ def with_species(params, types, a_tab, g_tab):
     q.ntypes, q.type, q.a_tab, q.g_tab = nt, _p(t, ctypes.c_int32), _p(a, ctypes.c_double), _p(g, ctypes.c_double)
     q._keep = (t, a, g)
     return q
+
+
+def with_walls(params, kind, h, frozen=None, body_uniform=True):
+    """Copy of params with walls: kind 1 = two plates normal to grad_axis
+    (fluid where |y - L/2| < h), 2 = a pipe of radius h along flow_axis
+    through the box centre; frozen[i] = 1 marks a wall particle.  The body
+    force becomes uniform unless body_uniform is False."""
+    q = Params()
+    ctypes.pointer(q)[0] = params
+    keep = list(getattr(params, "_keep", ()))
+    q.wall_kind, q.wall_h, q.body_uniform = int(kind), float(h), int(bool(body_uniform))
+    if frozen is not None:
+        fz = np.ascontiguousarray(frozen, dtype=np.uint8)
+        q.frozen = _p(fz, ctypes.c_uint8)
+        keep.append(fz)
+    q._keep = tuple(keep)
+    return q
+
+
+def sdf(points, cells, params):
+    """The oracle's signed wall distance at each point (negative in the fluid)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    L = lib()
+    return np.array([L.orc_sdf(_p(pts[k], ctypes.c_double), _p(c, ctypes.c_int32), ctypes.byref(params))
+                     for k in range(len(pts))])
 
 
 def philox4x32_10(ctr, key):

@@ -17,6 +17,8 @@
  *   - cell lists (edge r_c, sort by cell)  Sec. 3.2
  *   - fused velocity-Verlet (kick, drift)  Sec. 3.1, time-stepping step 5
  *   - periodic Poiseuille body force ..... Sec. 4.2, Eq. (11)
+ *   - walls: SDF surface, frozen particles, Sec. 2.3; bounce-back at the
+ *     SDF's zero along the drift, Sec. 3.3
  *   - several species with their own a and gamma per pair of species
  *     (fluids of different viscosity side by side: Sec. 2.3, Sec. 5.2,
  *     Sec. 5.3); kT, dt, the mass and the kernels stay shared
@@ -58,6 +60,15 @@ typedef struct {
     const int32_t* type; /* species of each particle (row of x), ntypes > 1 */
     const double* a_tab; /* ntypes x ntypes, symmetric: a of species pair  */
     const double* g_tab; /* ntypes x ntypes, symmetric: gamma of the pair  */
+    int32_t body_uniform; /* 1: body force +f along flow_axis everywhere (pipe
+                             or channel flow); 0: Eq. 11's two halves        */
+    int32_t wall_kind;   /* walls (Sec. 2.3): 0 none; 1 two plates normal to
+                            grad_axis, fluid where |y - L/2| < wall_h; 2 a pipe
+                            along flow_axis through the box centre, fluid
+                            where the distance to its axis is < wall_h       */
+    double wall_h;       /* plate half-gap or pipe radius                    */
+    const uint8_t* frozen; /* per particle: 1 = frozen wall particle, which
+                              interacts but never moves; NULL = none         */
 } orc_params;
 
 typedef struct {
@@ -271,10 +282,12 @@ int orc_pair_force(const double ri[3], const double rj[3], const double vi[3], c
 }
 
 /* Periodic-Poiseuille body force (Sec. 4.2, Eq. 11): -f along the flow
- * axis where the gradient coordinate is <= L/2, +f otherwise. */
+ * axis where the gradient coordinate is <= L/2, +f otherwise; or a uniform
+ * +f (body_uniform), the drive of flow between walls. */
 static double orc_body_force(const double* r, const int32_t cells[3], const orc_params* p)
 {
     if (p->body_f == 0.0) return 0.0;
+    if (p->body_uniform) return p->body_f;
     double half = 0.5 * (double)cells[p->grad_axis];
     return r[p->grad_axis] <= half ? -p->body_f : p->body_f;
 }
@@ -359,6 +372,47 @@ static void orc_force_on(int64_t i, int64_t n, const double* x, const double* v,
     *virial_half = vir;
 }
 
+/* Signed distance to the wall surface (Sec. 2.3): negative in the fluid,
+ * zero on the wall surface, positive inside the wall. */
+double orc_sdf(const double* r, const int32_t cells[3], const orc_params* p)
+{
+    if (p->wall_kind == 1) {
+        double y = r[p->grad_axis] - 0.5 * (double)cells[p->grad_axis];
+        return fabs(y) - p->wall_h;
+    }
+    if (p->wall_kind == 2) {
+        double q2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            if (k == p->flow_axis) continue;
+            double c = r[k] - 0.5 * (double)cells[k];
+            q2 += c * c;
+        }
+        return sqrt(q2) - p->wall_h;
+    }
+    return -1.0;
+}
+
+/* Bounce-back (Sec. 3.3): a particle whose drift from x0 by dx ends inside
+ * the wall is placed at the collision point, the zero of the SDF along the
+ * drift (found by bisection; the fluid-side end of the final bracket), and
+ * its velocity is reversed (the walls are at rest).  Returns 1 on a bounce. */
+static int orc_bounce(const double x0[3], const double dx[3], double x[3], double v[3], const int32_t cells[3],
+                      const orc_params* p)
+{
+    if (!p->wall_kind || orc_sdf(x, cells, p) <= 0.0) return 0;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double mid = 0.5 * (lo + hi), m[3];
+        for (int k = 0; k < 3; ++k) m[k] = x0[k] + mid * dx[k];
+        if (orc_sdf(m, cells, p) > 0.0) hi = mid; else lo = mid;
+    }
+    for (int k = 0; k < 3; ++k) {
+        x[k] = x0[k] + lo * dx[k];
+        v[k] = -v[k];
+    }
+    return 1;
+}
+
 static int orc_check(const int32_t cells[3], const orc_params* p)
 {
     for (int k = 0; k < 3; ++k)
@@ -368,6 +422,7 @@ static int orc_check(const int32_t cells[3], const orc_params* p)
     if (p->flow_axis < 0 || p->flow_axis > 2 || p->grad_axis < 0 || p->grad_axis > 2) return -1;
     if (p->flow_axis == p->grad_axis) return -1;
     if (p->ntypes < 0 || p->ntypes > 64) return -1;
+    if (p->wall_kind < 0 || p->wall_kind > 2 || (p->wall_kind && !(p->wall_h > 0.0))) return -1;
     if (p->ntypes > 1) {
         if (!p->type || !p->a_tab || !p->g_tab) return -1;
         for (int s = 0; s < p->ntypes; ++s)
@@ -438,8 +493,12 @@ int orc_forces(int64_t n, const double* x, const double* v, const uint32_t* id,
  *      v^{n-1/2} + dt f^n / (2m)), profile of the flow velocity over
  *      `nbins` slabs along the gradient axis;
  *   3. kick v^{n+1/2} = v^{n-1/2} + dt f^n / m, then drift
- *      x^{n+1} = x^n + dt v^{n+1/2}, then periodic wrap;
+ *      x^{n+1} = x^n + dt v^{n+1/2}, bounce-back off the walls (Sec. 3.3),
+ *      then periodic wrap;
  *   4. momentum and KE of v^{n+1/2}.
+ * Frozen wall particles (Sec. 2.3) take part in the forces only: they are
+ * neither moved nor counted in the diagnostics (kT uses 3 (N_fluid - 1)
+ * degrees of freedom) or the profile.
  * diag (nsteps entries), prof_sum / prof_cnt (nbins, accumulated) and
  * f_last (n x 3, forces of the last step) may each be NULL. */
 int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t cells[3],
@@ -450,6 +509,10 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
     if (n < 2 || nsteps < 0) return -1;
     double box[3] = {(double)cells[0], (double)cells[1], (double)cells[2]};
     double vol = box[0] * box[1] * box[2];
+    int64_t nfluid = n;                 /* diagnostics cover the moving particles only */
+    if (p->frozen)
+        for (int64_t i = 0; i < n; ++i) nfluid -= p->frozen[i] ? 1 : 0;
+    if (nfluid < 2) return -1;
     double* f = (double*)malloc((size_t)n * 3 * sizeof(double));
     double* s = (double*)malloc((size_t)n * sizeof(double));
     if (!f || !s) { free(f); free(s); return -2; }
@@ -460,6 +523,7 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
         if (rc) { free(f); free(s); return rc; }
         double ke_c = 0.0;
         for (int64_t i = 0; i < n; ++i) {
+            if (p->frozen && p->frozen[i]) continue;
             double vc[3];
             for (int k = 0; k < 3; ++k) vc[k] = v[3 * i + k] + 0.5 * p->dt * f[3 * i + k] / p->mass;
             ke_c += 0.5 * p->mass * (vc[0] * vc[0] + vc[1] * vc[1] + vc[2] * vc[2]);
@@ -474,16 +538,22 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
         }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
+            if (p->frozen && p->frozen[i]) continue;          /* wall particles stay put */
+            double x0[3], dx[3];
             for (int k = 0; k < 3; ++k) {
                 v[3 * i + k] += p->dt * f[3 * i + k] / p->mass;
-                x[3 * i + k] += p->dt * v[3 * i + k];
-                x[3 * i + k] -= box[k] * floor(x[3 * i + k] / box[k]);
+                x0[k] = x[3 * i + k];
+                dx[k] = p->dt * v[3 * i + k];
+                x[3 * i + k] += dx[k];
             }
+            orc_bounce(x0, dx, x + 3 * i, v + 3 * i, cells, p);
+            for (int k = 0; k < 3; ++k) x[3 * i + k] -= box[k] * floor(x[3 * i + k] / box[k]);
         }
         if (diag) {
             orc_diag* dg = diag + it;
             double mom[3] = {0.0, 0.0, 0.0}, ke_h = 0.0;
             for (int64_t i = 0; i < n; ++i) {
+                if (p->frozen && p->frozen[i]) continue;
                 double* vi = v + 3 * i;
                 for (int k = 0; k < 3; ++k) mom[k] += p->mass * vi[k];
                 ke_h += 0.5 * p->mass * (vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
@@ -491,7 +561,7 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
             for (int k = 0; k < 3; ++k) dg->momentum[k] = mom[k];
             dg->ke_half = ke_h;
             dg->ke_centred = ke_c;
-            dg->kT_centred = 2.0 * ke_c / (3.0 * (double)(n - 1));
+            dg->kT_centred = 2.0 * ke_c / (3.0 * (double)(nfluid - 1));
             dg->virial = virial;
             dg->pressure = ((double)n / vol) * dg->kT_centred + virial / (3.0 * vol);
         }
