@@ -204,6 +204,44 @@ def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
     return out
 
 
+def bench_walls(steps=500, warmup=30, R=20.0, length=48):
+    """Pipe flow: the rho = 3 fluid of the main workload in a pipe of radius
+    20 along x (frozen wall layer cut from the equilibrated fluid, uniform
+    drive, bounce-back), 48 cells long.  Throughput over all particles (the
+    frozen ones are binned and take part in every force) and per stage."""
+    import torch
+    from paper_1911_04712_amd import dpd, walls
+    side = int(math.ceil(2 * (R + 1.0))) + 2
+    cells = (length, side, side)
+    base = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    pos, vel, frozen = walls.carve(cells, 3.0, base, dpd.WALL_PIPE, R, seed=9, equil_steps=200)
+    p = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, body_f=0.002, flags=dpd.FLAG_BODY_UNIFORM,
+                        wall_kind=dpd.WALL_PIPE, wall_h=R)
+    box = dpd.Box(cells, len(pos), params=p, seed=9)
+    box.set_state(pos, vel)
+    box.set_frozen(frozen)
+    tile = list(box.tune_tile(reps=5)[0])
+    box.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    box.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = box.stats()
+    inside = float(box.wall_sdf()[~frozen].max())
+    stage = box.profile_steps(50)
+    box.close()
+    n = len(pos)
+    return {"workload": f"pipe R={R:g} along x, {length} cells long, cells {list(cells)}, rho=3, "
+                        f"frozen wall layer, bounce-back, uniform drive",
+            "particles": n, "frozen": int(frozen.sum()), "value": n * steps / (ms / 1e3), "unit": "particle-steps/s",
+            "fluid_particle_steps_per_s": int((~frozen).sum()) * steps / (ms / 1e3), "steps": steps, "tile": tile,
+            "ms_per_step": ms / steps, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+            "kT_centred_last": st["kT_centred"], "max_fluid_sdf": inside, "nonfinite": st["nonfinite"]}
+
+
 def bench_served(nreq=1000, quantum=50, pool_gb=32, max_slots=256):
     """Poisson trace of requests (mean 200/s, edges log-uniform [8, 48], rho 3
     or 8, 500 steps): continuous batching vs FIFO one request at a time."""
@@ -282,6 +320,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-species", action="store_true", help="skip the two-species measurement")
+    ap.add_argument("--no-walls", action="store_true", help="skip the pipe-flow (walls) measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device copy of this many MiB (reference for HBM counters)")
@@ -386,6 +425,8 @@ def main():
     box.close()
     if not args.no_species:
         out["species"] = bench_species(w, check=not args.no_cpu_baseline)
+    if not args.no_walls:
+        out["walls"] = bench_walls()
     if not args.no_batched:
         out["batched"] = bench_batched()
     if not args.no_served:

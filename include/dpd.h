@@ -83,9 +83,20 @@ enum {
 /* flags of dpd_params.flags */
 enum {
     DPD_FLAG_VIRIAL = 1,          /* also accumulate the conservative virial each step   */
-    DPD_FLAG_REFERENCE_FORCE = 2  /* use the one-thread-per-particle gather kernel for
+    DPD_FLAG_REFERENCE_FORCE = 2, /* use the one-thread-per-particle gather kernel for
                                      the pair forces instead of the LDS tile kernel (same
                                      bits; a reference for validation)                    */
+    DPD_FLAG_BODY_UNIFORM = 4     /* body force +body_f along flow_axis everywhere (flow
+                                     between walls) instead of Eq. 11's two halves        */
+};
+
+/* walls of dpd_params.wall_kind (Sec. 2.3): the wall surface is the zero of a
+ * signed distance function, negative in the fluid */
+enum {
+    DPD_WALL_NONE = 0,
+    DPD_WALL_PLATES = 1,  /* two plates normal to grad_axis: sdf = |y - L_y/2| - wall_h   */
+    DPD_WALL_PIPE = 2     /* a pipe along flow_axis through the box centre:
+                             sdf = (distance to the axis) - wall_h                      */
 };
 
 typedef struct dpd_box_s* dpd_box;
@@ -118,6 +129,14 @@ typedef struct {
                              the dissipative kernel is w_D = w_R^2 and the
                              conservative weight stays 1 - r (Sec. 2.1).
                              0 < k <= 1; 0 selects k = 1                           */
+    int32_t wall_kind;    /* DPD_WALL_*: a fluid particle whose drift ends inside the
+                             wall (sdf > 0) is put back at the collision point, the
+                             sdf's zero along the drift, with its velocity reversed
+                             (bounce-back, Sec. 3.3)                               */
+    int32_t reserved2;    /* must be 0                                             */
+    double wall_h;        /* plate half-gap or pipe radius; the wall and its frozen
+                             layer (thickness r_c = 1) must fit inside the box:
+                             wall_h + 1 < L/2 on every axis the sdf depends on     */
 } dpd_params;
 
 /* Diagnostics, all reduced in FP64 on the GPU in a fixed order.
@@ -126,7 +145,7 @@ typedef struct {
     double momentum[3];       /* last: sum m v^{n+1/2}                                 */
     double ke_half;           /* last: sum m |v^{n+1/2}|^2 / 2                        */
     double ke_centred;        /* last: sum m |v^{n-1/2} + dt f^n/(2m)|^2 / 2           */
-    double kT_centred;        /* last: 2 ke_centred / (3 (N - 1))                     */
+    double kT_centred;        /* last: 2 ke_centred / (3 (N - 1)), N = free particles  */
     double virial;            /* last: sum_{i<j} r_ij . F^C_ij (DPD_FLAG_VIRIAL)      */
     double pressure;          /* last: rho kT_centred + virial / (3 V)                */
     double sum_kT_centred;    /* sums over the steps since the last reset ...         */
@@ -181,6 +200,24 @@ int dpd_set_types(dpd_box box, const int32_t* type_host);
 /* Read the species back, row i = particle id i (host array of n int32).
  * Synchronises. */
 int dpd_get_types(dpd_box box, int32_t* type_host);
+
+/* Frozen wall particles (Sec. 2.3): frozen_host[i] != 0 marks particle id i
+ * (host array of n bytes) as part of a wall's frozen layer.  Frozen
+ * particles take part in every pair force but never move (their velocity is
+ * set to 0, the walls being at rest), and are left out of the momentum,
+ * kinetic energy, kT (3 (N_fluid - 1) degrees of freedom) and flow profile.
+ * dpd_set_state and dpd_init_random clear the marks.  DPD_ESTATE without a
+ * state; DPD_EINVAL if fewer than 2 particles stay free.  Synchronises. */
+int dpd_set_frozen(dpd_box box, const uint8_t* frozen_host);
+
+/* The frozen marks, row i = particle id i (host array of n bytes, 0 or 1). */
+int dpd_get_frozen(dpd_box box, uint8_t* frozen_host);
+
+/* Signed wall distance of every particle's current position, row i =
+ * particle id i (host array of n floats; negative in the fluid), for the
+ * box's wall_kind and wall_h (DPD_ESTATE when the params name no wall).
+ * Frozen layers are cut from an equilibrated fluid with it.  Synchronises. */
+int dpd_wall_sdf(dpd_box box, float* sdf_host);
 
 /* Cell-tile shape of the LDS pair-force kernel: tile[3] edges in cells
  * (each 1..16), or {0, 0, 0} for the default chosen from the density.

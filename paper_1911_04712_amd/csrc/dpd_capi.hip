@@ -144,6 +144,8 @@ struct dpd_box_s {
     double a_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
     double g_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
     int max_type = 0;          // largest species assigned since the state was loaded
+    int n_frozen = 0;          // frozen wall particles of the current state
+    double rho_occ = 0.0;      // particles per occupied cell of the loaded state (0: use n / nc)
 
     // captured multi-step graph
     hipStream_t cap_stream = nullptr;
@@ -202,6 +204,7 @@ dpd::ForceConst force_const(const dpd_box_s* b)
     fc.flow_axis = p.flow_axis;
     fc.grad_axis = p.grad_axis;
     fc.half_grad = 0.5f * b->L[p.grad_axis];
+    fc.body_uniform = (p.flags & DPD_FLAG_BODY_UNIFORM) ? 1 : 0;
     return fc;
 }
 
@@ -223,7 +226,11 @@ dpd::StepConst step_const(const dpd_box_s* b)
     sc.nbins = p.profile_bins;
     sc.grad_scale = (float)((double)p.profile_bins / (double)b->cells[p.grad_axis]);
     sc.mass = p.mass;
-    sc.inv_dof = b->n >= 2 ? 1.0 / (3.0 * (double)(b->n - 1)) : 0.0;
+    const int nfree = b->n - b->n_frozen;
+    sc.inv_dof = nfree >= 2 ? 1.0 / (3.0 * (double)(nfree - 1)) : 0.0;
+    sc.wall_kind = p.wall_kind;
+    sc.wall_h = (float)p.wall_h;
+    for (int k = 0; k < 3; ++k) sc.centre[k] = 0.5f * b->L[k];
     const double vol = (double)b->cells[0] * b->cells[1] * b->cells[2];
     sc.inv_vol = 1.0 / vol;
     sc.rho = (double)b->n / vol;
@@ -235,14 +242,23 @@ dpd::StepConst step_const(const dpd_box_s* b)
 dpd::TileConst tile_for(const dpd_box_s* b, const int* req)
 {
     int t[3] = {req[0], req[1], req[2]};
-    if (t[0] <= 0) {
-        const double rho = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
-        const bool dilute = rho <= 4.5;
-        t[0] = 4;
-        t[1] = dilute ? 4 : 2;
-        t[2] = dilute ? 4 : 2;
+    // the tile capacities follow the density of the occupied cells: a box
+    // with walls leaves the cells beyond the frozen layers empty
+    // (unless that would not fit a CU's LDS, as for a clump of particles:
+    // overfull tiles then take the gather path)
+    const double rho_mean = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
+    for (const double rho : {b->rho_occ > 1.1 * rho_mean ? b->rho_occ : rho_mean, rho_mean}) {
+        int u[3] = {t[0], t[1], t[2]};
+        if (u[0] <= 0) {
+            const bool dilute = rho <= 4.5;
+            u[0] = 4;
+            u[1] = dilute ? 4 : 2;
+            u[2] = dilute ? 4 : 2;
+        }
+        const dpd::TileConst tc = dpd::make_tile_const(b->cells, rho, u, 0, 0);
+        if ((size_t)tc.lds_bytes <= kLdsLimit || rho == rho_mean) return tc;
     }
-    return dpd::make_tile_const(b->cells, b->n, t, 0, 0);
+    return dpd::TileConst{};   // not reached
 }
 
 // Rebuild the host descriptor and single-box plan from the box's current
@@ -277,6 +293,7 @@ int push_desc(dpd_box_s* b)
     }
     d.tc = tile_for(b, b->tile_req);
     int pre[dpd::kNumWork * 2];
+    const dpd::LaunchPlan old = b->lp;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         pre[2 * k] = 0;
         pre[2 * k + 1] = dpd::box_work(d, k);
@@ -289,6 +306,12 @@ int push_desc(dpd_box_s* b)
     b->lp.any_virial = (d.flags & DPD_FLAG_VIRIAL) != 0;
     b->lp.reference_force = (d.flags & DPD_FLAG_REFERENCE_FORCE) != 0;
     b->lp.species = d.fc.ntypes > 1;
+    b->lp.walls = d.sc.wall_kind != 0 || b->n_frozen > 0;
+    // a captured graph holds the kernel choice and the launch shapes
+    if (old.lds_force != b->lp.lds_force || old.any_virial != b->lp.any_virial ||
+        old.reference_force != b->lp.reference_force || old.species != b->lp.species || old.walls != b->lp.walls)
+        b->graph_dirty = true;
+    for (int k = 0; k < dpd::kNumWork; ++k) b->graph_dirty |= old.total[k] != b->lp.total[k];
     HIPCHK(dpd::force_tiled_prepare(d.tc.lds_bytes));
     HIPCHK(hipMemcpyAsync(b->d_desc, &d, sizeof d, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_pre, pre, sizeof pre, hipMemcpyHostToDevice, b->stream));
@@ -424,7 +447,20 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
         return fail(DPD_EINVAL, "dpd_set_params: flow_axis and grad_axis must be distinct axes in 0..2");
     if (p->profile_bins < 0 || p->profile_bins > dpd::kProfileMaxBins)
         return fail(DPD_EINVAL, "dpd_set_params: profile_bins must be in [0, %d]", dpd::kProfileMaxBins);
-    if (p->flags & ~(DPD_FLAG_VIRIAL | DPD_FLAG_REFERENCE_FORCE)) return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
+    if (p->flags & ~(DPD_FLAG_VIRIAL | DPD_FLAG_REFERENCE_FORCE | DPD_FLAG_BODY_UNIFORM))
+        return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
+    if (p->wall_kind < DPD_WALL_NONE || p->wall_kind > DPD_WALL_PIPE || p->reserved2 != 0)
+        return fail(DPD_EINVAL, "dpd_set_params: wall_kind must be a DPD_WALL_* value and reserved2 0");
+    if (p->wall_kind != DPD_WALL_NONE) {
+        if (!std::isfinite(p->wall_h) || !(p->wall_h > 0.0))
+            return fail(DPD_EINVAL, "dpd_set_params: wall_h must be finite and > 0");
+        for (int k = 0; k < 3; ++k) {
+            const bool used = p->wall_kind == DPD_WALL_PLATES ? k == p->grad_axis : k != p->flow_axis;
+            if (used && !(p->wall_h + 1.0 < 0.5 * b->cells[k]))
+                return fail(DPD_EINVAL, "dpd_set_params: the wall and its frozen layer must fit: wall_h + 1 < L/2 "
+                            "on axis %d", k);
+        }
+    }
     if (!(p->kexp >= 0.0 && p->kexp <= 1.0)) return fail(DPD_EINVAL, "dpd_set_params: kexp must be in [0, 1]");
     const double sig = std::sqrt(2.0 * p->gamma * p->kT) / std::sqrt(p->dt);
     if (!std::isfinite(sig) || sig > 1e8 || std::fabs(p->a) > 1e8 || p->gamma > 1e8)
@@ -506,6 +542,51 @@ int dpd_get_types(dpd_box b, int32_t* type_host)
     return sync_box(b);
 }
 
+int dpd_set_frozen(dpd_box b, const uint8_t* frozen_host)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_set_frozen: null box");
+    if (!b->have_state) return fail(DPD_ESTATE, "dpd_set_frozen: no state loaded");
+    if (b->n > 0 && !frozen_host) return fail(DPD_EINVAL, "dpd_set_frozen: null array");
+    int nf = 0;
+    for (int i = 0; i < b->n; ++i) nf += frozen_host[i] ? 1 : 0;
+    if (b->n - nf < 2) return fail(DPD_EINVAL, "dpd_set_frozen: at least 2 particles must stay free");
+    const dpd::BoxDesc& d = b->hd;
+    unsigned char* staged = (unsigned char*)b->out;
+    HIPCHK(hipMemcpyAsync(staged, frozen_host, (size_t)b->n, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(dpd::launch_set_frozen(d.pos_a, d.vel_a, b->n, staged, b->stream));
+    if (b->binned || b->have_force)     // pos_b / vel_b hold a copy of the state in cell order
+        HIPCHK(dpd::launch_set_frozen(d.pos_b, d.vel_b, b->n, staged, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->n_frozen = nf;
+    return push_desc(b);                // degrees of freedom of kT
+}
+
+int dpd_get_frozen(dpd_box b, uint8_t* frozen_host)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_get_frozen: null box");
+    if (!b->have_state) return fail(DPD_ESTATE, "dpd_get_frozen: no state loaded");
+    if (b->n > 0 && !frozen_host) return fail(DPD_EINVAL, "dpd_get_frozen: null array");
+    if (b->n == 0) return DPD_OK;
+    const dpd::BoxDesc& d = b->hd;
+    unsigned char* staged = (unsigned char*)b->out;
+    HIPCHK(dpd::launch_get_frozen(d.pos_a, d.vel_a, b->n, staged, b->stream));
+    HIPCHK(hipMemcpyAsync(frozen_host, staged, (size_t)b->n, hipMemcpyDeviceToHost, b->stream));
+    return sync_box(b);
+}
+
+int dpd_wall_sdf(dpd_box b, float* sdf_host)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_wall_sdf: null box");
+    if (!b->have_state || !b->have_params) return fail(DPD_ESTATE, "dpd_wall_sdf: needs params and a state");
+    if (b->params.wall_kind == DPD_WALL_NONE) return fail(DPD_ESTATE, "dpd_wall_sdf: the params name no wall");
+    if (b->n > 0 && !sdf_host) return fail(DPD_EINVAL, "dpd_wall_sdf: null array");
+    if (b->n == 0) return DPD_OK;
+    const dpd::BoxDesc& d = b->hd;
+    HIPCHK(dpd::launch_wall_sdf(d.pos_a, b->n, d.sc, b->out, b->stream));
+    HIPCHK(hipMemcpyAsync(sdf_host, b->out, (size_t)b->n * sizeof(float), hipMemcpyDeviceToHost, b->stream));
+    return sync_box(b);
+}
+
 int dpd_set_tile(dpd_box b, const int32_t tile[3])
 {
     if (!b || !tile) return fail(DPD_EINVAL, "dpd_set_tile: null argument");
@@ -541,7 +622,8 @@ int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where
     if (where != DPD_HOST && where != DPD_DEVICE) return fail(DPD_EINVAL, "dpd_set_state: bad `where`");
     if (b->n > 0 && (!pos_n3 || !vel_n3)) return fail(DPD_EINVAL, "dpd_set_state: null array");
     b->have_state = b->keys_valid = b->binned = b->have_force = false;
-    b->max_type = 0;                                   // every particle starts as species 0
+    b->max_type = 0;                                   // every particle starts as species 0, free
+    b->n_frozen = 0;
     const dpd::BoxDesc& d = b->hd;
     const float *pp = pos_n3, *vp = vel_n3;
     const size_t bytes = (size_t)b->n * 3 * sizeof(float);
@@ -558,10 +640,14 @@ int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where
     HIPCHK(dpd::launch_load_state(pp, vp, b->n, d.pos_a, d.vel_a, (float)b->q, (float)(1.0 / b->q), b->L, b->flags,
                                   b->stream));
     HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
-    int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, b->flags, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(dpd::launch_count_nonempty(d.count, b->nc, b->flags + 1, b->stream));
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, b->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    if (bad) return fail(DPD_EINVAL, "dpd_set_state: a position is outside [0, L) or a value is non-finite");
+    if (bad[0]) return fail(DPD_EINVAL, "dpd_set_state: a position is outside [0, L) or a value is non-finite");
+    b->rho_occ = bad[1] > 0 ? (double)b->n / (double)bad[1] : 0.0;
+    const int rc = push_desc(b);        // capacities, no frozen particles
+    if (rc) return rc;
     b->have_state = true;
     b->keys_valid = true;
     return DPD_OK;
@@ -573,7 +659,8 @@ int dpd_init_random(dpd_box b, double kT, uint64_t seed)
     if (!b->have_params) return fail(DPD_ESTATE, "dpd_init_random: set params first (the mass scales velocities)");
     if (!std::isfinite(kT) || kT < 0.0) return fail(DPD_EINVAL, "dpd_init_random: kT must be finite and >= 0");
     b->have_state = b->keys_valid = b->binned = b->have_force = false;
-    b->max_type = 0;                                   // every particle starts as species 0
+    b->max_type = 0;                                   // every particle starts as species 0, free
+    b->n_frozen = 0;
     const dpd::BoxDesc& d = b->hd;
     HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
     HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
@@ -585,6 +672,9 @@ int dpd_init_random(dpd_box b, double kT, uint64_t seed)
                                    (double*)b->out, scratch, b->stream));
     HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
+    b->rho_occ = 0.0;                   // uniform positions
+    const int rc = push_desc(b);        // no frozen particles
+    if (rc) return rc;
     b->have_state = true;
     b->keys_valid = true;
     return DPD_OK;
@@ -854,16 +944,18 @@ int batch_refresh(dpd_batch_s* bt)
     std::vector<dpd::BoxDesc> h(nb);
     bt->pre.assign((size_t)dpd::kNumWork * (nb + 1), 0);
     int lds = 0;
-    bool virial = false, species = false;
+    bool virial = false, species = false, walls = false;
     for (int i = 0; i < nb; ++i) {
         h[i] = bt->boxes[i]->hd;
         lds = std::max(lds, h[i].tc.lds_bytes);
         virial |= (h[i].flags & DPD_FLAG_VIRIAL) != 0;
         species |= h[i].fc.ntypes > 1;
+        walls |= bt->boxes[i]->lp.walls;
         for (int k = 0; k < dpd::kNumWork; ++k)
             bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
     }
-    bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species;
+    bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species ||
+                   bt->lp.walls != walls;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
         changed |= bt->lp.total[k] != tot;
@@ -875,6 +967,7 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.lds_force = lds;
     bt->lp.any_virial = virial;
     bt->lp.species = species;
+    bt->lp.walls = walls;
     bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
     if (changed) bt->graph_steps = 0;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));

@@ -44,6 +44,7 @@ __device__ __forceinline__ int wrap_cell(int c, int L) { return c < 0 ? c + L : 
 
 __device__ __forceinline__ float body_force_of(float4 p, const ForceConst& fc)
 {
+    if (fc.body_uniform) return fc.body_f;
     const float g = fc.grad_axis == 0 ? p.x : (fc.grad_axis == 1 ? p.y : p.z);
     return g <= fc.half_grad ? -fc.body_f : fc.body_f;
 }
@@ -345,8 +346,8 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
             const float4 p1 = gload4(pos, src[1]), v1 = gload4(vel, src[1]);
             sp[s0] = make_float4(p0.x + shx[0], p0.y + shy[0], p0.z + shz[0], p0.w);
             if constexpr (kSp) {
-                tiv[0] = (tiv[0] & 0xffffff) | (__float_as_int(v0.w) << 24);
-                tiv[1] = (tiv[1] & 0xffffff) | (__float_as_int(v1.w) << 24);
+                tiv[0] = (tiv[0] & 0xffffff) | (int)((unsigned)__float_as_int(v0.w) << 24);   // species bits
+                tiv[1] = (tiv[1] & 0xffffff) | (int)((unsigned)__float_as_int(v1.w) << 24);
             }
             sv[s0] = make_float4(v0.x, v0.y, v0.z, __int_as_float(tiv[0]));
             const int s1 = s0 + (int)blockDim.x;
@@ -492,17 +493,14 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
     }
 }
 
-TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax_override, int pmax_override)
+TileConst make_tile_const(const int* cells, double rho, const int* tile, int smax_override, int pmax_override)
 {
     TileConst tc{};
-    int64_t nc = 1;
     for (int k = 0; k < 3; ++k) {
         tc.T[k] = tile[k] < cells[k] ? tile[k] : cells[k];
         tc.ntile[k] = (cells[k] + tc.T[k] - 1) / tc.T[k];
-        nc *= cells[k];
     }
     tc.ntiles = tc.ntile[0] * tc.ntile[1] * tc.ntile[2];
-    const double rho = nc > 0 ? (double)n / (double)nc : 0.0;
     const int ncs_max = (tc.T[0] + 2) * (tc.T[1] + 2) * (tc.T[2] + 2);
     const int ntc = tc.T[0] * tc.T[1] * tc.T[2];
     // capacities: mean + 6 standard deviations of a uniform fluid, rounded up

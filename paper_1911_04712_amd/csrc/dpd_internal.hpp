@@ -17,6 +17,8 @@ constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred
 constexpr int kFlagVirial = 1;          // DPD_FLAG_VIRIAL
 constexpr int kFlagReference = 2;       // DPD_FLAG_REFERENCE_FORCE
 constexpr int kMaxTypes = 8;            // species of one box (DPD_MAX_TYPES)
+constexpr int kFrozenBit = 256;         // in the velocity's .w (an int): a frozen wall particle
+constexpr int kFlagBodyUniform = 4;     // DPD_FLAG_BODY_UNIFORM
 
 // Fixed-point scale of the flow-profile and virial accumulators.
 constexpr double kProfScale = 16777216.0;      // 2^24 units per velocity unit
@@ -53,10 +55,24 @@ struct StepConst {
     int flow_axis, grad_axis, nbins;
     float grad_scale;  // nbins / L_grad
     double mass;
-    double inv_dof;    // 1 / (3 (N - 1))  (0 when N < 2)
+    double inv_dof;    // 1 / (3 (N - 1)), N = particles not frozen  (0 when N < 2)
     double inv_vol;
     double rho;
+    int wall_kind;     // DPD_WALL_*
+    float wall_h;      // plate half-gap or pipe radius
+    float centre[3];   // L / 2
 };
+
+// Signed distance to the wall surface: negative in the fluid.
+__device__ __forceinline__ float wall_sdf(float x, float y, float z, const StepConst& sc)
+{
+    const float r[3] = {x - sc.centre[0], y - sc.centre[1], z - sc.centre[2]};
+    if (sc.wall_kind == 1) return fabsf(r[sc.grad_axis]) - sc.wall_h;
+    float q2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q2 += k == sc.flow_axis ? 0.0f : r[k] * r[k];
+    return sqrtf(q2) - sc.wall_h;
+}
 
 struct ForceConst {
     PairConst pc;
@@ -65,6 +81,7 @@ struct ForceConst {
     float body_f;
     int flow_axis, grad_axis;
     float half_grad;   // L_grad / 2
+    int body_uniform;  // 1: +body_f everywhere, 0: the two halves of Eq. 11
     int ntypes;        // species; > 1: each pair takes (a, gamma, sigma / sqrt(dt)) from tab
     float4 tab[kMaxTypes * kMaxTypes];   // [s * kMaxTypes + t], symmetric; unused entries 0
 };
@@ -122,6 +139,7 @@ struct LaunchPlan {
     int total[kNumWork];       // workgroups per kind
     int lds_force;             // dynamic LDS of the tile kernel (max over boxes)
     bool species;              // some box has several species: the tile kernel reads the pair table
+    bool walls;                // some box has walls or frozen particles: the wall integrate kernel
     bool any_virial;
     bool reference_force;      // single box flagged DPD_FLAG_REFERENCE_FORCE
 };
@@ -162,12 +180,18 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
 // species by id -> vel[i].w of the particle whose id is pos[i].w, and back
 hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s);
 hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* type_by_id, hipStream_t s);
+// frozen marks by id <-> the frozen bit of vel[i].w (frozen velocities set to 0)
+hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id, hipStream_t s);
+hipError_t launch_get_frozen(const float4* pos, const float4* vel, int n, unsigned char* frozen_by_id, hipStream_t s);
+hipError_t launch_wall_sdf(const float4* pos, int n, const StepConst& sc, float* sdf_by_id, hipStream_t s);
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_force(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s);
-TileConst make_tile_const(const int* cells, int64_t n, const int* tile, int smax_override, int pmax_override);
+// rho: particles per occupied cell (the density the tile capacities are sized for)
+TileConst make_tile_const(const int* cells, double rho, const int* tile, int smax_override, int pmax_override);
+hipError_t launch_count_nonempty(const int* count, int nc, int* out, hipStream_t s);
 hipError_t force_tiled_prepare(int lds_bytes);
 hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,
                           float* out3, hipStream_t s);

@@ -207,6 +207,24 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
     return hipGetLastError();
 }
 
+// Number of cells holding at least one particle (added to *out).
+__global__ __launch_bounds__(kBlock) void k_count_nonempty(const int* __restrict__ count, int nc, int* __restrict__ out)
+{
+    __shared__ long long scratch[kBlock / 64];
+    long long k = 0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) k += count[c] > 0 ? 1 : 0;
+    k = block_sum(k, scratch);
+    if (threadIdx.x == 0 && k) atomicAdd(out, (int)k);
+}
+
+hipError_t launch_count_nonempty(const int* count, int nc, int* out, hipStream_t s)
+{
+    if (nc <= 0) return hipSuccess;
+    const int blocks = (nc + kBlock - 1) / kBlock < 1024 ? (nc + kBlock - 1) / kBlock : 1024;
+    hipLaunchKernelGGL(k_count_nonempty, dim3(blocks), dim3(kBlock), 0, s, count, nc, out);
+    return hipGetLastError();
+}
+
 // Species by particle id into the .w of the velocity row holding that id.
 __global__ void k_set_types(const float4* __restrict__ pos, float4* __restrict__ vel, int n,
                             const int* __restrict__ type_by_id)
@@ -214,7 +232,8 @@ __global__ void k_set_types(const float4* __restrict__ pos, float4* __restrict__
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int id = __float_as_int(pos[i].w);
-    vel[i].w = __int_as_float(type_by_id[id]);
+    const int w = __float_as_int(vel[i].w);
+    vel[i].w = __int_as_float(type_by_id[id] | (w & kFrozenBit));
 }
 
 __global__ void k_get_types(const float4* __restrict__ pos, const float4* __restrict__ vel, int n,
@@ -222,7 +241,38 @@ __global__ void k_get_types(const float4* __restrict__ pos, const float4* __rest
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    type_by_id[__float_as_int(pos[i].w)] = __float_as_int(vel[i].w);
+    type_by_id[__float_as_int(pos[i].w)] = __float_as_int(vel[i].w) & 0xff;
+}
+
+__global__ void k_set_frozen(const float4* __restrict__ pos, float4* __restrict__ vel, int n,
+                             const unsigned char* __restrict__ frozen_by_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 v = vel[i];
+    const int w = __float_as_int(v.w) & ~kFrozenBit;
+    if (frozen_by_id[__float_as_int(pos[i].w)]) {
+        v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(w | kFrozenBit));   // walls at rest
+    } else {
+        v.w = __int_as_float(w);
+    }
+    vel[i] = v;
+}
+
+__global__ void k_get_frozen(const float4* __restrict__ pos, const float4* __restrict__ vel, int n,
+                             unsigned char* __restrict__ frozen_by_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    frozen_by_id[__float_as_int(pos[i].w)] = (__float_as_int(vel[i].w) & kFrozenBit) ? 1 : 0;
+}
+
+__global__ void k_wall_sdf(const float4* __restrict__ pos, int n, StepConst sc, float* __restrict__ sdf_by_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = pos[i];
+    sdf_by_id[__float_as_int(p.w)] = wall_sdf(p.x, p.y, p.z, sc);
 }
 
 hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s)
@@ -236,6 +286,27 @@ hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* ty
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_get_types, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, type_by_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_frozen, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, frozen_by_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_frozen(const float4* pos, const float4* vel, int n, unsigned char* frozen_by_id, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_get_frozen, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, frozen_by_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_sdf(const float4* pos, int n, const StepConst& sc, float* sdf_by_id, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wall_sdf, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, n, sc, sdf_by_id);
     return hipGetLastError();
 }
 
@@ -432,7 +503,11 @@ hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s)
 // fused velocity-Verlet + next keys + FP64 reductions
 // ---------------------------------------------------------------------------
 constexpr int kLdsBins = 1024;
+constexpr int kBounceIters = 24;        // bisection steps of the bounce-back: t to 2^-24 of the drift
 
+// kWalls: some box of the launch has walls (bounce-back and frozen particles);
+// the plain instantiation keeps the register budget of the wall-free step.
+template <bool kWalls>
 __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
                                                       int nbox)
 {
@@ -467,10 +542,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             v = vel_s[i];
             f = force[i];
         }
+        const bool frozen = kWalls && (__float_as_int(v.w) & kFrozenBit) != 0;   // wall particles never move
         const float vcx = fmaf(f.x, sc.half_dtm, v.x), vcy = fmaf(f.y, sc.half_dtm, v.y),
                     vcz = fmaf(f.z, sc.half_dtm, v.z);
-        const float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
-        float nx = fmaf(vx, sc.dt, x.x), ny = fmaf(vy, sc.dt, x.y), nz = fmaf(vz, sc.dt, x.z);
+        float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
+        if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
+        float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
+              nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
         const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) &&
                          isfinite(nz);
         if (!fin) {
@@ -481,6 +559,26 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         nx = rintf(nx * sc.inv_q) * sc.q;
         ny = rintf(ny * sc.inv_q) * sc.q;
         nz = rintf(nz * sc.inv_q) * sc.q;
+        if (kWalls && sc.wall_kind != 0 && live && !frozen && fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
+            // bounce-back: bisection for the sdf's zero along the drift, every
+            // probe on the position grid; the particle goes to the last probe
+            // on the fluid side (the start, t = 0, if none) and its velocity is
+            // reversed (walls at rest)
+            const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
+            float lo = 0.0f, hi = 1.0f;
+            for (int it = 0; it < kBounceIters; ++it) {
+                const float mid = 0.5f * (lo + hi);
+                const bool in = wall_sdf(rintf(fmaf(mid, dx, x.x) * sc.inv_q) * sc.q,
+                                         rintf(fmaf(mid, dy, x.y) * sc.inv_q) * sc.q,
+                                         rintf(fmaf(mid, dz, x.z) * sc.inv_q) * sc.q, sc) > 0.0f;
+                lo = in ? lo : mid;
+                hi = in ? mid : hi;
+            }
+            nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
+            ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
+            nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
+            vx = -vx; vy = -vy; vz = -vz;
+        }
         if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
         if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
         if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
@@ -496,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             pos_a[i] = make_float4(nx, ny, nz, x.w);
             vel_a[i] = make_float4(vx, vy, vz, v.w);              // .w: species
         }
-        if (live && fin) {
+        if (live && fin && !frozen) {
             m[0] += (double)vx;
             m[1] += (double)vy;
             m[2] += (double)vz;
@@ -629,7 +727,10 @@ __global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict
 
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_integrate, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    if (lp.walls)
+        hipLaunchKernelGGL(k_integrate<true>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    else
+        hipLaunchKernelGGL(k_integrate<false>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ HOST, DEVICE = 0, 1
 POS, VEL, VEL_CENTRED, FORCE = 0, 1, 2, 3
 FLAG_VIRIAL = 1
 FLAG_REFERENCE_FORCE = 2
+FLAG_BODY_UNIFORM = 4
+WALL_NONE, WALL_PLATES, WALL_PIPE = 0, 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE",
           EAGAIN: "EAGAIN", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND"}
@@ -38,7 +40,8 @@ class Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
                 ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32),
-                ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32), ("kexp", ctypes.c_double)]
+                ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32), ("kexp", ctypes.c_double),
+                ("wall_kind", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("wall_h", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -100,6 +103,9 @@ SIGNATURES = {
     "dpd_set_species": ([_VP, ctypes.c_int32, _VP, _VP], ctypes.c_int),
     "dpd_get_species": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_set_types": ([_VP, _VP], ctypes.c_int),
+    "dpd_set_frozen": ([_VP, _VP], ctypes.c_int),
+    "dpd_get_frozen": ([_VP, _VP], ctypes.c_int),
+    "dpd_wall_sdf": ([_VP, _VP], ctypes.c_int),
     "dpd_get_types": ([_VP, _VP], ctypes.c_int),
     "dpd_build_cells": ([_VP], ctypes.c_int),
     "dpd_step": ([_VP, _I64], ctypes.c_int),
@@ -173,10 +179,11 @@ def batch_workspace_bytes(nboxes):
 
 
 def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1,
-                profile_bins=0, flags=0, kexp=1.0):
-    """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1)."""
+                profile_bins=0, flags=0, kexp=1.0, wall_kind=0, wall_h=0.0):
+    """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1).
+    wall_kind: WALL_NONE, WALL_PLATES (half-gap wall_h) or WALL_PIPE (radius wall_h)."""
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f), int(flow_axis),
-                  int(grad_axis), int(profile_bins), int(flags), float(kexp))
+                  int(grad_axis), int(profile_bins), int(flags), float(kexp), int(wall_kind), 0, float(wall_h))
 
 
 def _as_arg(arr, dtype, shape_tail):
@@ -276,6 +283,24 @@ class Box:
         t = np.empty(self.n, dtype=np.int32)
         _check(lib().dpd_get_types(self._h, t.ctypes.data))
         return t
+
+    def set_frozen(self, frozen):
+        """Mark wall particles: frozen[i] true freezes particle id i."""
+        f = np.ascontiguousarray(np.asarray(frozen).astype(bool), dtype=np.uint8)
+        if f.shape != (self.n,):
+            raise ValueError(f"frozen must have shape ({self.n},)")
+        _check(lib().dpd_set_frozen(self._h, f.ctypes.data))
+
+    def get_frozen(self):
+        f = np.empty(self.n, dtype=np.uint8)
+        _check(lib().dpd_get_frozen(self._h, f.ctypes.data))
+        return f.astype(bool)
+
+    def wall_sdf(self):
+        """Signed wall distance of every particle (id order; negative in the fluid)."""
+        out = np.empty(self.n, dtype=np.float32)
+        _check(lib().dpd_wall_sdf(self._h, out.ctypes.data))
+        return out
 
     def init_random(self, kT, seed):
         """Random state generated on the device (uniform positions, Maxwellian
