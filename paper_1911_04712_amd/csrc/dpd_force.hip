@@ -441,27 +441,8 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
             const float bx = valid ? xb.x : 1e30f;
             const unsigned ub = (unsigned)u;
             const unsigned qdummy = (unsigned)(kQueueLive + lane);
-            for (int a = own_s; a < own_e; a += 2) {
-                const bool two = a + 1 < own_e;     // uniform
-                const float4 xa0 = sp[a];           // same address on every lane
-                const float4 xa1 = sp[two ? a + 1 : a];
-                const float r20 = dist2(xa0.x - bx, xa0.y - xb.y, xa0.z - xb.z);
-                const float r21 = dist2(xa1.x - bx, xa1.y - xb.y, xa1.z - xb.z);
-                // r2 < 1 (r2 == 0 adds nothing: see pair_fx), and list position
-                // after a (the unit heads the list)
-                const unsigned ia = (unsigned)(a - own_s);
-                const unsigned long long m0 = __builtin_amdgcn_ballot_w64(r20 < 1.0f) &
-                                              __builtin_amdgcn_ballot_w64(ub > ia);
-                const unsigned long long m1 = __builtin_amdgcn_ballot_w64(r21 < 1.0f) &
-                                              __builtin_amdgcn_ballot_w64(ub > ia + 1u) & (two ? ~0ull : 0ull);
-                const int c0 = __popcll(m0);
-                const unsigned s0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m0, (unsigned)qt));
-                const unsigned s1 = __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m1, (unsigned)(qt + c0)));
-                q[__builtin_amdgcn_inverse_ballot_w64(m0) ? s0 : qdummy] = ((unsigned)a << 16) | (unsigned)b;
-                q[__builtin_amdgcn_inverse_ballot_w64(m1) ? s1 : qdummy] = ((unsigned)(a + 1) << 16) | (unsigned)b;
-                qt += c0 + __popcll(m1);
+            // flush whole waves of hits once 64 or more are queued
+            auto drain = [&]() {
                 if (qt >= 64) {
                     __builtin_amdgcn_wave_barrier();
                     int fh = 0;
@@ -475,6 +456,43 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
                     __builtin_amdgcn_wave_barrier();
                     qt -= fh;
                 }
+            };
+            // home particles two at a time (the pair loop carries no odd-tail
+            // logic), then the odd one
+            int a = own_s;
+            for (; a + 1 < own_e; a += 2) {
+                const float4* pa = sp + a;          // same address on every lane
+                const float4 xa0 = pa[0];
+                const float4 xa1 = pa[1];
+                const float r20 = dist2(xa0.x - bx, xa0.y - xb.y, xa0.z - xb.z);
+                const float r21 = dist2(xa1.x - bx, xa1.y - xb.y, xa1.z - xb.z);
+                // r2 < 1 (r2 == 0 adds nothing: see pair_fx), and list position
+                // after a (the unit heads the list)
+                const unsigned ia = (unsigned)(a - own_s);
+                const unsigned long long m0 = __builtin_amdgcn_ballot_w64(r20 < 1.0f) &
+                                              __builtin_amdgcn_ballot_w64(ub > ia);
+                const unsigned long long m1 = __builtin_amdgcn_ballot_w64(r21 < 1.0f) &
+                                              __builtin_amdgcn_ballot_w64(ub > ia + 1u);
+                const int c0 = __popcll(m0);
+                const unsigned s0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m0, (unsigned)qt));
+                const unsigned s1 = __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m1, (unsigned)(qt + c0)));
+                q[__builtin_amdgcn_inverse_ballot_w64(m0) ? s0 : qdummy] = ((unsigned)a << 16) | (unsigned)b;
+                q[__builtin_amdgcn_inverse_ballot_w64(m1) ? s1 : qdummy] = ((unsigned)(a + 1) << 16) | (unsigned)b;
+                qt += c0 + __popcll(m1);
+                drain();
+            }
+            if (a < own_e) {
+                const float4 xa0 = sp[a];
+                const float r20 = dist2(xa0.x - bx, xa0.y - xb.y, xa0.z - xb.z);
+                const unsigned long long m0 = __builtin_amdgcn_ballot_w64(r20 < 1.0f) &
+                                              __builtin_amdgcn_ballot_w64(ub > (unsigned)(a - own_s));
+                const unsigned s0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m0, (unsigned)qt));
+                q[__builtin_amdgcn_inverse_ballot_w64(m0) ? s0 : qdummy] = ((unsigned)a << 16) | (unsigned)b;
+                qt += __popcll(m0);
+                drain();
             }
         }
     }
