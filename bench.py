@@ -95,10 +95,12 @@ def bench_batched(nboxes=64, steps=500, tune=True):
             tb = dpd.Box(s["cells"], s["n"], params=params, seed=0)
             tb.init_random(1.0, 1)
             tb.step(2)
-            tiles[key] = tb.tune_tile(reps=3)[0]
+            tiles[key] = (tb.tune_tile(reps=3)[0], tb.get_force_threads())
             tb.close()
         for b, s in zip(boxes, specs):
-            b.set_tile(tiles[(tuple(s["cells"]), s["n"])])
+            t, th = tiles[(tuple(s["cells"]), s["n"])]
+            b.set_tile(t)
+            b.set_force_threads(th)
     t_tune = time.perf_counter() - t_tune
 
     def reset():
@@ -128,6 +130,7 @@ def bench_batched(nboxes=64, steps=500, tune=True):
     reset()
     t_bt = time.perf_counter()
     btile, _ = batch.tune(reps=3)
+    bthreads = boxes[0].get_force_threads()
     t_bt = time.perf_counter() - t_bt
     reset()
     batch.step(steps)                  # capture + first run
@@ -148,8 +151,9 @@ def bench_batched(nboxes=64, steps=500, tune=True):
             "speedup_vs_plain": t_plain / t_batch, "speedup_vs_per_box_graph": t_boxgraph / t_batch,
             "seconds": {"batched": round(t_batch, 4), "plain": round(t_plain, 4), "per_box_graph": round(t_boxgraph, 4),
                         "autotune": round(t_tune, 3), "batch_autotune": round(t_bt, 3)},
-            "distinct_tiles": sorted({str(t) for t in tiles.values()}),
-            "batch_tile": list(btile) if btile else "per-box", "batched_equals_plain": same}
+            "distinct_tiles": sorted({f"{t} x{th}" for t, th in tiles.values()}),
+            "batch_tile": list(btile) if btile else "per-box", "batch_force_threads": bthreads,
+            "batched_equals_plain": same}
 
 
 def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
@@ -184,6 +188,7 @@ def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
     ach = force_ops(n, rho) / (stage["force"] / 1e3) / 1e12
     out = {"workload": f"{w.name} as two species (a = 25; gamma 4.5, 22.5 within, 0 across; half each)",
            "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "steps": steps, "tile": tile,
+           "force_threads": box.get_force_threads(),
            "ms_per_step": ms / steps, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
            "force_frac_of_alu_peak": round(ach / VALU_PEAK_TOPS, 4),
            "kT_centred_last": st["kT_centred"], "nonfinite": st["nonfinite"]}
@@ -232,12 +237,14 @@ def bench_walls(steps=500, warmup=30, R=20.0, length=48):
     st = box.stats()
     inside = float(box.wall_sdf()[~frozen].max())
     stage = box.profile_steps(50)
+    threads = box.get_force_threads()
     box.close()
     n = len(pos)
     return {"workload": f"pipe R={R:g} along x, {length} cells long, cells {list(cells)}, rho=3, "
                         f"frozen wall layer, bounce-back, uniform drive",
             "particles": n, "frozen": int(frozen.sum()), "value": n * steps / (ms / 1e3), "unit": "particle-steps/s",
             "fluid_particle_steps_per_s": int((~frozen).sum()) * steps / (ms / 1e3), "steps": steps, "tile": tile,
+            "force_threads": threads,
             "ms_per_step": ms / steps, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
             "kT_centred_last": st["kT_centred"], "max_fluid_sdf": inside, "nonfinite": st["nonfinite"]}
 
@@ -317,6 +324,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default cell tile of the force kernel")
     ap.add_argument("--tile", default="", help="cell tile of the force kernel, e.g. 6,3,3 (no autotuning)")
+    ap.add_argument("--threads", type=int, default=0, help="force-kernel workgroup size with --tile (256/512/1024)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-species", action="store_true", help="skip the two-species measurement")
@@ -347,6 +355,7 @@ def main():
     # outside the timed region; tiles never change results)
     if args.tile:
         box.set_tile(tuple(int(t) for t in args.tile.split(",")))
+        box.set_force_threads(args.threads)
         tile = list(box.get_tile())
     else:
         tile = list(box.tune_tile(reps=5)[0]) if not args.no_tune else list(box.get_tile())
@@ -383,6 +392,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "cells": list(w.cells), "particles": n, "density": rho, "tile": tile,
+                      "force_threads": box.get_force_threads(),
                       "a": w.a,
                       "gamma": w.gamma, "kT": w.kT, "dt": w.dt, "body_f": w.body_f, "reductions": "f64",
                       "parallelism": "single GPU"},

@@ -227,10 +227,21 @@ int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 /* The tile shape in use (after clamping to the box). */
 int dpd_get_tile(dpd_box box, int32_t tile[3]);
 
+/* Workgroup size of the LDS pair-force kernel: 256, 512 or 1024 threads
+ * (4, 8 or 16 waves sharing one tile), or 0 for the default 512.  Results
+ * do not depend on it (bitwise).  DPD_EINVAL for other values, or if the
+ * current tile would then need more LDS than a CU has. */
+int dpd_set_force_threads(dpd_box box, int32_t threads);
+
+/* The workgroup size in use. */
+int dpd_get_force_threads(dpd_box box, int32_t* threads);
+
 /* Autotuner: time the LDS pair-force kernel on the box's current positions
- * for a fixed list of tile shapes (those whose LDS fits a CU), `reps` launches
- * each with HIP events on the box stream, keep the fastest and report it in
- * tile_out and *ms_out (mean ms per force evaluation; may be NULL).  The
+ * for a fixed list of tile shapes, each with 256, 512 and 1024 threads per
+ * workgroup (those whose LDS fits a CU), `reps` launches each with HIP
+ * events on the box stream, keep the fastest pair and report the tile in
+ * tile_out (the workgroup size through dpd_get_force_threads) and *ms_out
+ * (mean ms per force evaluation; may be NULL).  The
  * state does not advance (the box is left holding its cell list, as after
  * dpd_build_cells) and, since results do not depend on the tile, no result
  * changes.  Synchronises. */
@@ -315,10 +326,12 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
 /* Batch autotuner: bins every box once and times the batched pair-force
  * launch (`reps` launches per configuration, HIP events on the batch stream)
  * for the boxes' current tiles and for each tile shape of the single-box
- * list applied to all boxes (skipping shapes whose LDS does not fit a CU
- * for some box); keeps the fastest.  tile_out receives the uniform tile, or
- * {0, 0, 0} when the boxes' own tiles were fastest; *ms_out (may be NULL) the
- * mean ms per batched force evaluation.  Boxes must have params, seed and
+ * list applied to all boxes, each with 256, 512 and 1024 threads per
+ * workgroup (skipping configurations whose LDS does not fit a CU for some
+ * box); keeps the fastest.  tile_out receives the uniform tile, or
+ * {0, 0, 0} when the boxes' own tiles were fastest, and every box the
+ * winning workgroup size (one launch has one; a batch runs with its first
+ * box's); *ms_out (may be NULL) the mean ms per batched force evaluation.  Boxes must have params, seed and
  * state and must not hold a bare cell list; afterwards every box holds its
  * cell list (dpd_batch_step then starts from it).  No result changes: the
  * state does not advance and results do not depend on the tile.

@@ -138,6 +138,7 @@ struct dpd_box_s {
     bool have_force = false;   // force/pos_b hold the last step's forces
 
     int tile_req[3] = {0, 0, 0};
+    int threads_req = 0;       // workgroup size of the tile kernel (0: kForceBlock)
 
     // species: ntypes = 0 uses params.a / params.gamma for every pair
     int ntypes = 0;
@@ -239,8 +240,9 @@ dpd::StepConst step_const(const dpd_box_s* b)
 
 // Default cell tile of the LDS force kernel (measured on MI355X): 4x4x4
 // cells at solvent densities up to 4.5, 4x2x2 above.
-dpd::TileConst tile_for(const dpd_box_s* b, const int* req)
+dpd::TileConst tile_for(const dpd_box_s* b, const int* req, int threads = 0)
 {
+    if (threads <= 0) threads = b->threads_req > 0 ? b->threads_req : dpd::kForceBlock;
     int t[3] = {req[0], req[1], req[2]};
     // the tile capacities follow the density of the occupied cells: a box
     // with walls leaves the cells beyond the frozen layers empty
@@ -255,7 +257,7 @@ dpd::TileConst tile_for(const dpd_box_s* b, const int* req)
             u[1] = dilute ? 4 : 2;
             u[2] = dilute ? 4 : 2;
         }
-        const dpd::TileConst tc = dpd::make_tile_const(b->cells, rho, u, 0, 0);
+        const dpd::TileConst tc = dpd::make_tile_const(b->cells, rho, u, threads, 0, 0);
         if ((size_t)tc.lds_bytes <= kLdsLimit || rho == rho_mean) return tc;
     }
     return dpd::TileConst{};   // not reached
@@ -303,13 +305,15 @@ int push_desc(dpd_box_s* b)
     b->lp.pre = b->d_pre;
     b->lp.nbox = 1;
     b->lp.lds_force = d.tc.lds_bytes;
+    b->lp.force_threads = d.tc.threads;
     b->lp.any_virial = (d.flags & DPD_FLAG_VIRIAL) != 0;
     b->lp.reference_force = (d.flags & DPD_FLAG_REFERENCE_FORCE) != 0;
     b->lp.species = d.fc.ntypes > 1;
     b->lp.walls = d.sc.wall_kind != 0 || b->n_frozen > 0;
     // a captured graph holds the kernel choice and the launch shapes
     if (old.lds_force != b->lp.lds_force || old.any_virial != b->lp.any_virial ||
-        old.reference_force != b->lp.reference_force || old.species != b->lp.species || old.walls != b->lp.walls)
+        old.reference_force != b->lp.reference_force || old.species != b->lp.species || old.walls != b->lp.walls ||
+        old.force_threads != b->lp.force_threads)
         b->graph_dirty = true;
     for (int k = 0; k < dpd::kNumWork; ++k) b->graph_dirty |= old.total[k] != b->lp.total[k];
     HIPCHK(dpd::force_tiled_prepare(d.tc.lds_bytes));
@@ -601,6 +605,27 @@ int dpd_set_tile(dpd_box b, const int32_t tile[3])
     return push_desc(b);
 }
 
+int dpd_set_force_threads(dpd_box b, int32_t threads)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_set_force_threads: null box");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(DPD_EINVAL, "dpd_set_force_threads: threads must be 0, 256, 512 or 1024");
+    const int saved = b->threads_req;
+    b->threads_req = threads;
+    if ((size_t)tile_for(b, b->tile_req).lds_bytes > kLdsLimit) {
+        b->threads_req = saved;
+        return fail(DPD_EINVAL, "dpd_set_force_threads: the tile would need more LDS than a CU has");
+    }
+    return push_desc(b);
+}
+
+int dpd_get_force_threads(dpd_box b, int32_t* threads)
+{
+    if (!b || !threads) return fail(DPD_EINVAL, "dpd_get_force_threads: null argument");
+    *threads = b->hd.tc.threads;
+    return DPD_OK;
+}
+
 int dpd_get_tile(dpd_box b, int32_t tile[3])
 {
     if (!b || !tile) return fail(DPD_EINVAL, "dpd_get_tile: null argument");
@@ -772,15 +797,19 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     }
     const auto& cand = kTuneCand;
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
+    const int saved_threads = b->threads_req;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     double best = 1e300;
-    int bt[3] = {0, 0, 0};
+    int bt[3] = {0, 0, 0}, bthreads = 0;
     int rc = DPD_OK;
+    for (const int threads : dpd::kForceBlocks)
     for (const auto& c : cand) {
-        if ((size_t)tile_for(b, c).lds_bytes > kLdsLimit) continue;
+        if (rc) break;
+        if ((size_t)tile_for(b, c, threads).lds_bytes > kLdsLimit) continue;
         for (int k = 0; k < 3; ++k) b->tile_req[k] = c[k];
+        b->threads_req = threads;
         rc = push_desc(b);
         if (rc) break;
         float ms = 0.0f;
@@ -798,11 +827,14 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         if (per < best) {
             best = per;
             for (int k = 0; k < 3; ++k) bt[k] = b->hd.tc.T[k];
+            bthreads = threads;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (int k = 0; k < 3; ++k) b->tile_req[k] = rc == DPD_OK && bt[0] > 0 ? bt[k] : saved[k];
+    const bool won = rc == DPD_OK && bt[0] > 0;
+    for (int k = 0; k < 3; ++k) b->tile_req[k] = won ? bt[k] : saved[k];
+    b->threads_req = won ? bthreads : saved_threads;
     b->have_force = false;
     b->graph_dirty = true;
     const int rc2 = push_desc(b);
@@ -945,8 +977,12 @@ int batch_refresh(dpd_batch_s* bt)
     bt->pre.assign((size_t)dpd::kNumWork * (nb + 1), 0);
     int lds = 0;
     bool virial = false, species = false, walls = false;
+    // one launch has one workgroup size: the first box's; the others are
+    // laid out for it in the batch's copy of their descriptors
+    const int threads = nb > 0 ? bt->boxes[0]->hd.tc.threads : dpd::kForceBlock;
     for (int i = 0; i < nb; ++i) {
         h[i] = bt->boxes[i]->hd;
+        if (h[i].tc.threads != threads) h[i].tc = tile_for(bt->boxes[i], bt->boxes[i]->tile_req, threads);
         lds = std::max(lds, h[i].tc.lds_bytes);
         virial |= (h[i].flags & DPD_FLAG_VIRIAL) != 0;
         species |= h[i].fc.ntypes > 1;
@@ -955,7 +991,7 @@ int batch_refresh(dpd_batch_s* bt)
             bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
     }
     bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species ||
-                   bt->lp.walls != walls;
+                   bt->lp.walls != walls || bt->lp.force_threads != threads;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
         changed |= bt->lp.total[k] != tot;
@@ -968,6 +1004,7 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.any_virial = virial;
     bt->lp.species = species;
     bt->lp.walls = walls;
+    bt->lp.force_threads = threads;
     bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
     if (changed) bt->graph_steps = 0;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));
@@ -1037,26 +1074,32 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
         b->graph_dirty = true;
     }
     std::vector<std::array<int, 3>> saved;
-    for (dpd_box_s* b : bt->boxes) saved.push_back({b->tile_req[0], b->tile_req[1], b->tile_req[2]});
+    std::vector<int> saved_threads;
+    for (dpd_box_s* b : bt->boxes) {
+        saved.push_back({b->tile_req[0], b->tile_req[1], b->tile_req[2]});
+        saved_threads.push_back(b->threads_req);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     double best = 1e300;
-    int bt3[3] = {0, 0, 0};
+    int bt3[3] = {0, 0, 0}, bthreads = 0;
     bool have_best = false;
     const int ncand = (int)(sizeof kTuneCand / sizeof kTuneCand[0]);
+    for (const int threads : dpd::kForceBlocks)
     for (int ci = -1; ci < ncand && rc == DPD_OK; ++ci) {      // -1: the boxes' own tiles
         bool fits = true;
         for (size_t i = 0; i < bt->boxes.size() && fits; ++i) {
             dpd_box_s* b = bt->boxes[i];
             const int* t = ci < 0 ? saved[i].data() : kTuneCand[ci];
-            fits = (size_t)tile_for(b, t).lds_bytes <= kLdsLimit;
+            fits = (size_t)tile_for(b, t, threads).lds_bytes <= kLdsLimit;
         }
         if (!fits) continue;
         for (size_t i = 0; i < bt->boxes.size() && rc == DPD_OK; ++i) {
             dpd_box_s* b = bt->boxes[i];
             const int* t = ci < 0 ? saved[i].data() : kTuneCand[ci];
             for (int k = 0; k < 3; ++k) b->tile_req[k] = t[k];
+            b->threads_req = threads;
             rc = push_desc(b);
         }
         if (rc == DPD_OK) rc = batch_refresh(bt);
@@ -1077,6 +1120,7 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
             best = per;
             have_best = true;
             for (int k = 0; k < 3; ++k) bt3[k] = ci < 0 ? 0 : kTuneCand[ci][k];
+            bthreads = threads;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1085,8 +1129,10 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
     int rc2 = DPD_OK;
     for (size_t i = 0; i < bt->boxes.size() && rc2 == DPD_OK; ++i) {
         dpd_box_s* b = bt->boxes[i];
-        const bool uniform = rc == DPD_OK && have_best && bt3[0] > 0;
+        const bool ok = rc == DPD_OK && have_best;
+        const bool uniform = ok && bt3[0] > 0;
         for (int k = 0; k < 3; ++k) b->tile_req[k] = uniform ? bt3[k] : saved[i][k];
+        b->threads_req = ok ? bthreads : saved_threads[i];
         rc2 = push_desc(b);
     }
     if (rc2 == DPD_OK) rc2 = batch_refresh(bt);

@@ -211,8 +211,8 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
     }
 }
 
-template <bool kSp>
-__global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __restrict__ desc,
+template <bool kSp, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restrict__ desc,
                                                              const int* __restrict__ pre, int nbox)
 {
     const int* __restrict__ pre_ = pre + kWTile * (nbox + 1);
@@ -233,11 +233,11 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
     int* cg = (int*)(lds + tc.off_cg);                          // staged cell start in HBM (cell order)
     int4* rows = (int4*)(lds + tc.off_rows);                    // tile rows: (lds start, len, HBM start, tile start)
     unsigned* qall = (unsigned*)(lds + tc.off_q);               // per-wave hit queues
-    __shared__ int s_scr[kForceBlock / 64];
+    __shared__ int s_scr[kThreads / 64];
     const float4* tab = nullptr;                                // species pair table (kSp)
     if constexpr (kSp) {
         __shared__ float4 s_tab[kMaxTypes * kMaxTypes];
-        for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += blockDim.x) s_tab[k] = fc.tab[k];
+        for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += kThreads) s_tab[k] = fc.tab[k];
         tab = s_tab;                                            // visible after the first barrier below
     }
 
@@ -254,14 +254,14 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
     const int P0 = min(tc.T[0], L0 - o0), P1 = min(tc.T[1], L1 - o1), P2 = min(tc.T[2], L2 - o2);
     const int S0 = P0 + 2, S1 = P1 + 2, S2 = P2 + 2;
     const int ncs = S0 * S1 * S2;
-    const int tid = threadIdx.x, lane = tid & 63, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, nw = kThreads >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const float inv_s0 = 1.0f / (float)S0, inv_s1 = 1.0f / (float)S1, inv_p1 = 1.0f / (float)P1;
     const uint32_t step = (uint32_t)d.st->step;
 
     // 1. HBM start and particle count of every staged cell (the only
     //    dependent HBM round trip before the copy), scanned into LDS offsets
-    for (int lc = tid; lc < ncs; lc += blockDim.x) {
+    for (int lc = tid; lc < ncs; lc += kThreads) {
         const int rr = small_div(lc, inv_s0);                  // staged row
         const int lz = small_div(rr, inv_s1), ly = rr - lz * S1, lx = lc - rr * S0;
         const int g = wrap_cell(o0 - 1 + lx, L0) + L0 * (wrap_cell(o1 - 1 + ly, L1) + L1 * wrap_cell(o2 - 1 + lz, L2));
@@ -320,12 +320,12 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
         int top = 1;
         while (top * 2 <= nsrows) top *= 2;
         const float shx_lo = o0 == 0 ? -fc.L[0] : 0.0f, shx_hi = o0 + P0 == L0 ? fc.L[0] : 0.0f;
-        for (int s0 = tid; s0 < S; s0 += 2 * (int)blockDim.x) {
+        for (int s0 = tid; s0 < S; s0 += 2 * kThreads) {
             int src[2], tiv[2];
             float shx[2], shy[2], shz[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int s = min(s0 + u * (int)blockDim.x, S - 1);
+                const int s = min(s0 + u * kThreads, S - 1);
                 int r = 0;
                 for (int st = top; st > 0; st >>= 1)
                     if (r + st < nsrows && cst[(r + st) * S0] <= s) r += st;
@@ -350,14 +350,14 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
                 tiv[1] = (tiv[1] & 0xffffff) | (int)((unsigned)__float_as_int(v1.w) << 24);
             }
             sv[s0] = make_float4(v0.x, v0.y, v0.z, __int_as_float(tiv[0]));
-            const int s1 = s0 + (int)blockDim.x;
+            const int s1 = s0 + kThreads;
             if (s1 < S) {
                 sp[s1] = make_float4(p1.x + shx[1], p1.y + shy[1], p1.z + shz[1], p1.w);
                 sv[s1] = make_float4(v1.x, v1.y, v1.z, __int_as_float(tiv[1]));
             }
         }
     }
-    for (int k = tid; k < 3 * nt; k += blockDim.x) acc[k] = 0;
+    for (int k = tid; k < 3 * nt; k += kThreads) acc[k] = 0;
     __syncthreads();
 
     // 4. candidates, one home unit per wave at a time: ux consecutive cells
@@ -511,9 +511,11 @@ __global__ __launch_bounds__(kForceBlock) void k_force_tiled(const BoxDesc* __re
     }
 }
 
-TileConst make_tile_const(const int* cells, double rho, const int* tile, int smax_override, int pmax_override)
+TileConst make_tile_const(const int* cells, double rho, const int* tile, int threads, int smax_override,
+                          int pmax_override)
 {
     TileConst tc{};
+    tc.threads = threads;
     for (int k = 0; k < 3; ++k) {
         tc.T[k] = tile[k] < cells[k] ? tile[k] : cells[k];
         tc.ntile[k] = (cells[k] + tc.T[k] - 1) / tc.T[k];
@@ -541,9 +543,26 @@ TileConst make_tile_const(const int* cells, double rho, const int* tile, int sma
     tc.off_rows = (int)off;
     off += (size_t)tc.T[1] * tc.T[2] * 16;
     tc.off_q = (int)off;
-    off += (size_t)(kForceBlock / 64) * kQueue * 4;
+    off += (size_t)(threads / 64) * kQueue * 4;
     tc.lds_bytes = (int)off;
     return tc;
+}
+
+template <bool kSp>
+static void launch_tiled(const LaunchPlan& lp, hipStream_t s)
+{
+    const dim3 grid(lp.total[kWTile]);
+    switch (lp.force_threads) {
+    case 256:
+        hipLaunchKernelGGL((k_force_tiled<kSp, 256>), grid, dim3(256), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        break;
+    case 1024:
+        hipLaunchKernelGGL((k_force_tiled<kSp, 1024>), grid, dim3(1024), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        break;
+    default:
+        hipLaunchKernelGGL((k_force_tiled<kSp, 512>), grid, dim3(512), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        break;
+    }
 }
 
 hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
@@ -553,11 +572,9 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
             hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
         if (lp.species)
-            hipLaunchKernelGGL(k_force_tiled<true>, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc,
-                               lp.pre, lp.nbox);
+            launch_tiled<true>(lp, s);
         else
-            hipLaunchKernelGGL(k_force_tiled<false>, dim3(lp.total[kWTile]), dim3(kForceBlock), lp.lds_force, s, lp.desc,
-                               lp.pre, lp.nbox);
+            launch_tiled<false>(lp, s);
     }
     return hipGetLastError();
 }
@@ -565,11 +582,14 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
 hipError_t force_tiled_prepare(int lds_bytes)
 {
     if (lds_bytes <= 65536) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_force_tiled<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       lds_bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_force_tiled<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    return e;
+    const void* fns[] = {(const void*)k_force_tiled<false, 256>, (const void*)k_force_tiled<false, 512>,
+                         (const void*)k_force_tiled<false, 1024>, (const void*)k_force_tiled<true, 256>,
+                         (const void*)k_force_tiled<true, 512>, (const void*)k_force_tiled<true, 1024>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace dpd

@@ -9,7 +9,8 @@
 namespace dpd {
 
 constexpr int kBlock = 256;             // threads per block of the streaming kernels
-constexpr int kForceBlock = 512;        // threads per workgroup of the tiled pair-force kernel
+constexpr int kForceBlock = 512;        // default threads per workgroup of the tiled pair-force kernel
+constexpr int kForceBlocks[3] = {256, 512, 1024};   // the instantiated workgroup sizes
 constexpr int kScanChunk = 2048;        // cells per block of the cell-count scan
 constexpr int kIntegrateMaxBlocks = 2048;
 constexpr int kProfileMaxBins = 4096;
@@ -101,6 +102,7 @@ struct TileConst {
     int pmax;          // tile particles that fit the accumulators
     int lds_bytes;
     int off_sv, off_acc, off_cst, off_cg, off_rows, off_q;
+    int threads;       // workgroup size the queue region is laid out for (a kForceBlocks entry)
 };
 
 // Everything a kernel needs about one box, in device memory.  The step
@@ -138,6 +140,7 @@ struct LaunchPlan {
     int nbox;
     int total[kNumWork];       // workgroups per kind
     int lds_force;             // dynamic LDS of the tile kernel (max over boxes)
+    int force_threads;         // workgroup size of the tile kernel (every box's tc.threads)
     bool species;              // some box has several species: the tile kernel reads the pair table
     bool walls;                // some box has walls or frozen particles: the wall integrate kernel
     bool any_virial;
@@ -190,7 +193,8 @@ hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s);
 // rho: particles per occupied cell (the density the tile capacities are sized for)
-TileConst make_tile_const(const int* cells, double rho, const int* tile, int smax_override, int pmax_override);
+TileConst make_tile_const(const int* cells, double rho, const int* tile, int threads, int smax_override,
+                          int pmax_override);
 hipError_t launch_count_nonempty(const int* count, int nc, int* out, hipStream_t s);
 hipError_t force_tiled_prepare(int lds_bytes);
 hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale, const float4* idsrc, int n,

@@ -81,6 +81,8 @@ SIGNATURES = {
     "dpd_set_seed": ([_VP, ctypes.c_uint64], ctypes.c_int),
     "dpd_set_tile": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_get_tile": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "dpd_set_force_threads": ([_VP, ctypes.c_int32], ctypes.c_int),
+    "dpd_get_force_threads": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_tune_tile": ([_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
                       ctypes.c_int),
     "dpd_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -236,6 +238,15 @@ class Box:
         t = (ctypes.c_int32 * 3)()
         _check(lib().dpd_get_tile(self._h, t))
         return tuple(t)
+
+    def set_force_threads(self, threads):
+        """Workgroup size of the tile force kernel: 256, 512, 1024 (0: default)."""
+        _check(lib().dpd_set_force_threads(self._h, int(threads)))
+
+    def get_force_threads(self):
+        t = ctypes.c_int32()
+        _check(lib().dpd_get_force_threads(self._h, ctypes.byref(t)))
+        return t.value
 
     def tune_tile(self, reps=5):
         """Time the force kernel for the candidate tiles and keep the fastest.

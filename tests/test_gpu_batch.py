@@ -166,3 +166,33 @@ def test_autotuner_picks_a_tile_and_changes_no_bits():
         np.testing.assert_array_equal(tuned.read(what), ref.read(what))
     ref.close()
     tuned.close()
+
+
+def test_batch_of_boxes_with_other_workgroup_sizes_equals_alone():
+    # a batch launches with its first box's workgroup size; boxes tuned for
+    # another size are laid out for it in the batch's copy of their descriptors
+    cells = [(9, 8, 8), (12, 10, 7), (7, 6, 9)]
+    threads = [256, 1024, 512]
+    states = [inputs.uniform_state(c, density=3.0, seed=70 + k) for k, c in enumerate(cells)]
+    alone = []
+    for k, (c, (p, v)) in enumerate(zip(cells, states)):
+        b = dpd.Box(c, len(p), params=dpd.make_params(), seed=70 + k)
+        b.set_state(p, v)
+        b.step(6)
+        alone.append((b.read(dpd.POS), b.read(dpd.VEL)))
+        b.close()
+    boxes = []
+    for k, (c, (p, v)) in enumerate(zip(cells, states)):
+        b = dpd.Box(c, len(p), params=dpd.make_params(), seed=70 + k)
+        b.set_force_threads(threads[k])
+        b.set_state(p, v)
+        boxes.append(b)
+    batch = dpd.Batch(boxes)
+    batch.step(6)
+    for b, ref in zip(boxes, alone):
+        np.testing.assert_array_equal(b.read(dpd.POS), ref[0])
+        np.testing.assert_array_equal(b.read(dpd.VEL), ref[1])
+    assert [b.get_force_threads() for b in boxes] == threads      # the boxes keep their own setting
+    batch.close()
+    for b in boxes:
+        b.close()

@@ -12,11 +12,13 @@ from paper_1911_04712_amd import dpd, inputs
 pytestmark = pytest.mark.gpu
 
 
-def _run(cells, pos, vel, params, seed, steps, tile=None, reference=False):
+def _run(cells, pos, vel, params, seed, steps, tile=None, reference=False, threads=0):
     p = dpd.make_params(**params, flags=dpd.FLAG_REFERENCE_FORCE if reference else 0)
     b = dpd.Box(cells, len(pos), params=p, seed=seed)
     if tile is not None:
         b.set_tile(tile)
+    b.set_force_threads(threads)
+    assert b.get_force_threads() == (threads or 512)
     b.set_state(pos, vel)
     b.step(steps)
     out = (b.read(dpd.FORCE), b.read(dpd.POS), b.read(dpd.VEL))
@@ -52,6 +54,28 @@ def test_tile_shape_does_not_change_trajectory(tile):
     til = _run(cells, pos, vel, P3, 22, 20, tile=tile)
     for a, b in zip(til, ref):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("cells,rho,params,tile", [((12, 10, 9), 3.0, P3, (8, 3, 3)), ((12, 10, 9), 3.0, P3, (2, 2, 2)),
+                                                    ((9, 7, 6), 8.0, P8, (4, 2, 2)), ((9, 7, 6), 8.0, P8, (6, 4, 4))])
+def test_workgroup_size_does_not_change_trajectory(threads, cells, rho, params, tile):
+    # 4 or 16 waves share a tile instead of 8: other waves take other home
+    # units, the queue region is laid out for the launch's waves
+    pos, vel = inputs.uniform_state(cells, density=rho, seed=27)
+    ref = _run(cells, pos, vel, params, 27, 8, reference=True)
+    til = _run(cells, pos, vel, params, 27, 8, tile=tile, threads=threads)
+    for a, b in zip(til, ref):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_workgroup_size_errors():
+    b = dpd.Box((6, 6, 6), 648, params=dpd.make_params(), seed=1)
+    for bad in (128, 300, 2048, -1):
+        with pytest.raises(dpd.DPDError) as e:
+            b.set_force_threads(bad)
+        assert e.value.code == dpd.EINVAL
+    b.close()
 
 
 @pytest.mark.parametrize("tile", [(4, 2, 2), (3, 3, 3), (5, 2, 3)])
