@@ -358,7 +358,9 @@ int dpd_batch_destroy(dpd_batch batch);
  * one batch, retires finished ones (results copied to host memory, memory
  * freed) and admits waiting requests, so requests that arrive while others
  * run join the next quantum.  A request's result is the same bits alone or in
- * a mix. */
+ * a mix.  A request is one species without frozen particles: its params may
+ * name a wall (fluid particles then bounce off the SDF surface) but carry no
+ * frozen layer; species and frozen layers need a box of one's own. */
 typedef struct dpd_server_s* dpd_server;
 
 typedef struct {
