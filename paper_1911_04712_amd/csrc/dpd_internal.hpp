@@ -11,7 +11,7 @@ namespace dpd {
 constexpr int kBlock = 256;             // threads per block of the streaming kernels
 constexpr int kForceBlock = 512;        // default threads per workgroup of the tiled pair-force kernel
 constexpr int kForceBlocks[3] = {256, 512, 1024};   // the instantiated workgroup sizes
-constexpr int kScanChunk = 2048;        // cells per block of the cell-count scan
+constexpr int kScanChunk = 512;         // cells per block of the cell-count scan (2 per thread)
 constexpr int kIntegrateMaxBlocks = 2048;
 constexpr int kProfileMaxBins = 4096;
 constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred

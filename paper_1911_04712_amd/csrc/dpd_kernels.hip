@@ -359,7 +359,7 @@ __device__ void fold_stats(const BoxDesc& d);
 __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ desc, const int* __restrict__ pre, int nbox)
 {
     DPD_BOX_OF(kWChunk)
-    constexpr int per = kScanChunk / kBlock;   // 8 consecutive cells per thread
+    constexpr int per = kScanChunk / kBlock;   // consecutive cells per thread
     __shared__ int scratch[kBlock / 64];
     __shared__ int wtot[kBlock / 64];
     if (lb == d.nchunks) {                      // the extra block: the previous step's reductions
