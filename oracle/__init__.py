@@ -22,7 +22,8 @@ class Params(ctypes.Structure):
                 ("type", ctypes.POINTER(ctypes.c_int32)), ("a_tab", ctypes.POINTER(ctypes.c_double)),
                 ("g_tab", ctypes.POINTER(ctypes.c_double)),
                 ("body_uniform", ctypes.c_int32), ("wall_kind", ctypes.c_int32), ("wall_h", ctypes.c_double),
-                ("frozen", ctypes.POINTER(ctypes.c_uint8))]
+                ("frozen", ctypes.POINTER(ctypes.c_uint8)), ("rc", ctypes.c_double),
+                ("rc_tab", ctypes.POINTER(ctypes.c_double))]
 
 
 class Diag(ctypes.Structure):
@@ -77,10 +78,11 @@ def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_a
                   int(flow_axis), int(grad_axis), float(kexp))
 
 
-def with_species(params, types, a_tab, g_tab):
+def with_species(params, types, a_tab, g_tab, rc_tab=None):
     """Copy of params for a mixture: types[i] is the species of row i of the
-    state, a_tab / g_tab the symmetric ntypes x ntypes tables of a and gamma
-    per species pair.  The arrays are kept alive by the returned object."""
+    state, a_tab / g_tab (/ rc_tab) the symmetric ntypes x ntypes tables of
+    a, gamma (and the cutoff, <= 1) per species pair.  The arrays are kept
+    alive by the returned object."""
     t = np.ascontiguousarray(types, dtype=np.int32)
     a = np.ascontiguousarray(a_tab, dtype=np.float64)
     g = np.ascontiguousarray(g_tab, dtype=np.float64)
@@ -89,7 +91,13 @@ def with_species(params, types, a_tab, g_tab):
     q = Params()
     ctypes.pointer(q)[0] = params
     q.ntypes, q.type, q.a_tab, q.g_tab = nt, _p(t, ctypes.c_int32), _p(a, ctypes.c_double), _p(g, ctypes.c_double)
-    q._keep = (t, a, g)
+    keep = [t, a, g]
+    if rc_tab is not None:
+        c = np.ascontiguousarray(rc_tab, dtype=np.float64)
+        assert c.shape == (nt, nt)
+        q.rc_tab = _p(c, ctypes.c_double)
+        keep.append(c)
+    q._keep = tuple(keep)
     return q
 
 

@@ -19,9 +19,10 @@
  *   - periodic Poiseuille body force ..... Sec. 4.2, Eq. (11)
  *   - walls: SDF surface, frozen particles, Sec. 2.3; bounce-back at the
  *     SDF's zero along the drift, Sec. 3.3
- *   - several species with their own a and gamma per pair of species
- *     (fluids of different viscosity side by side: Sec. 2.3, Sec. 5.2,
- *     Sec. 5.3); kT, dt, the mass and the kernels stay shared
+ *   - several species with their own a, gamma and cutoff per pair of
+ *     species (fluids of different viscosity side by side: Sec. 2.3,
+ *     Sec. 5.2, Sec. 5.3; several cutoffs: Sec. 3.1); kT, dt and the mass
+ *     stay shared; cutoffs stay within the cell edge
  *   - random term: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
  *     random numbers: as easy as 1, 2, 3", SC'11) followed by the
  *     Box-Muller transform (Box & Muller 1958).  The paper names no
@@ -69,6 +70,10 @@ typedef struct {
     double wall_h;       /* plate half-gap or pipe radius                    */
     const uint8_t* frozen; /* per particle: 1 = frozen wall particle, which
                               interacts but never moves; NULL = none         */
+    double rc;           /* cutoff of the pair, 0 < rc <= 1 (the cell edge);
+                            0 means 1                                        */
+    const double* rc_tab; /* ntypes x ntypes, symmetric: cutoff per species
+                             pair (NULL: every pair at rc)                   */
 } orc_params;
 
 typedef struct {
@@ -239,11 +244,12 @@ int orc_bin(int64_t n, const float* pos3, const int32_t cells[3], int64_t* order
 /* ------------------------------------------------------------------ */
 
 /* Force on i from j.  Minimum-image displacement r_ij = r_i - r_j, unit
- * vector e_ij = r_ij / r_ij, weight w = 1 - r (r_c = 1, Eq. 4) of the
- * conservative term, random-term kernel w_R = w^k and dissipative kernel
- * w_D = w_R^2 (Sec. 2.1), v_ij = v_i - v_j, sigma = sqrt(2 gamma kT), and the
- * white noise discretised as xi / sqrt(dt).  Pairs at r >= r_c, and a pair
- * at r = 0 (where e_ij is undefined), contribute nothing.
+ * vector e_ij = r_ij / r_ij, weight w = 1 - r / r_c (Eq. 4; r_c = p->rc, 1
+ * unless a species pair sets its own) of the conservative term, random-term
+ * kernel w_R = w^k and dissipative kernel w_D = w_R^2 (Sec. 2.1),
+ * v_ij = v_i - v_j, sigma = sqrt(2 gamma kT), and the white noise
+ * discretised as xi / sqrt(dt).  Pairs at r >= r_c, and a pair at r = 0
+ * (where e_ij is undefined), contribute nothing.
  * Outputs: F (total pair force on i), Fc (conservative part), mag (sum of
  * the magnitudes of the three terms, the scale of the rounding error).
  * xi_ij is drawn for the pair's ids at force evaluation `step`.
@@ -261,9 +267,10 @@ int orc_pair_force(const double ri[3], const double rj[3], const double vi[3], c
     F[0] = F[1] = F[2] = 0.0;
     Fc[0] = Fc[1] = Fc[2] = 0.0;
     *mag = 0.0;
-    if (!(r2 < 1.0) || r2 == 0.0) return 0;
+    double rc = p->rc > 0.0 ? p->rc : 1.0;
+    if (!(r2 < rc * rc) || r2 == 0.0) return 0;
     double r = sqrt(r2);
-    double w = 1.0 - r;
+    double w = 1.0 - r / rc;
     double e[3] = {d[0] / r, d[1] / r, d[2] / r};
     double ev = e[0] * (vi[0] - vj[0]) + e[1] * (vi[1] - vj[1]) + e[2] * (vi[2] - vj[2]);
     double sigma = sqrt(2.0 * p->gamma * p->kT);
@@ -302,6 +309,7 @@ static orc_params orc_pair_params(const orc_params* p, int64_t i, int64_t j)
         int64_t k = (int64_t)p->type[i] * p->ntypes + p->type[j];
         q.a = p->a_tab[k];
         q.gamma = p->g_tab[k];
+        if (p->rc_tab) q.rc = p->rc_tab[k];
     }
     return q;
 }
@@ -430,8 +438,13 @@ static int orc_check(const int32_t cells[3], const orc_params* p)
                 double a = p->a_tab[s * p->ntypes + t], g = p->g_tab[s * p->ntypes + t];
                 if (!isfinite(a) || !isfinite(g) || g < 0.0) return -1;
                 if (a != p->a_tab[t * p->ntypes + s] || g != p->g_tab[t * p->ntypes + s]) return -1;
+                if (p->rc_tab) {
+                    double c = p->rc_tab[s * p->ntypes + t];
+                    if (!(c > 0.0 && c <= 1.0) || c != p->rc_tab[t * p->ntypes + s]) return -1;
+                }
             }
     }
+    if (!(p->rc >= 0.0 && p->rc <= 1.0)) return -1;
     return 0;
 }
 

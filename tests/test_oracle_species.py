@@ -15,7 +15,12 @@ here, none of it a retyped formula of the oracle's own code:
     each species' own centred temperature is kT (fluctuation-dissipation
     per pair: sigma_st^2 = 2 gamma_st kT);
   - the mean-field (weak a) pressure of a mixture is
-    rho kT + (pi / 30) sum_st rho_s rho_t a_st;
+    rho kT + (pi / 30) sum_st rho_s rho_t a_st, and with a cutoff per species
+    pair (Sec. 3.1 keeps several cutoffs) rho kT + (pi / 30) sum_st
+    rho_s rho_t a_st rc_st^4 (the virial integral of a (1 - r/rc) r^3 over
+    r < rc);
+  - a pair cutoff rc_st: force a_st (1 - r/rc_st) inside it, nothing beyond;
+    unit cutoffs reproduce the forces without a cutoff table bit for bit;
   - invalid tables and species are rejected.
 """
 import math
@@ -145,3 +150,71 @@ def test_invalid_species_rejected():
     for tt, a_tab, g_tab in bad:
         with pytest.raises(RuntimeError):
             oracle.forces(x, v, ids, cells, oracle.with_species(p, tt, a_tab, g_tab), 0, 0)
+
+
+def test_unit_cutoff_table_changes_no_bits():
+    cells = (6, 6, 6)
+    x, v, ids = _state(cells, 3.0, 36)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    types = inputs.species_types(len(x), [0.5, 0.5], seed=36)
+    a, g = [[25.0, 20.0], [20.0, 30.0]], [[4.5, 1.0], [1.0, 9.0]]
+    f0, _, _ = oracle.forces(x, v, ids, cells, oracle.with_species(p, types, a, g), 2, 5)
+    f1, _, _ = oracle.forces(x, v, ids, cells, oracle.with_species(p, types, a, g, np.ones((2, 2))), 2, 5)
+    assert np.array_equal(f0, f1)
+
+
+@pytest.mark.parametrize("r", [0.3, 0.7, 0.79, 0.85, 0.95])
+def test_pair_cutoff_closed_form(r):
+    a_tab = np.array([[10.0, 20.0], [20.0, 40.0]])
+    rc_tab = np.array([[1.0, 0.8], [0.8, 0.6]])
+    cells = (4, 4, 4)
+    x = np.array([[1.5, 1.5, 1.5], [1.5 + r, 1.5, 1.5]])
+    ids = np.arange(2, dtype=np.uint32)
+    p = oracle.make_params(a=0.0, gamma=0.0, kT=0.0, dt=0.01)
+    for s_, t_ in ((0, 0), (0, 1), (1, 1)):
+        q = oracle.with_species(p, [s_, t_], a_tab, np.zeros((2, 2)), rc_tab)
+        f, _, _ = oracle.forces(x, np.zeros((2, 3)), ids, cells, q, 0, 0)
+        rc = rc_tab[s_, t_]
+        want = a_tab[s_, t_] * (1.0 - r / rc) if r < rc else 0.0
+        assert f[1, 0] == pytest.approx(want, rel=1e-14, abs=1e-300)
+        assert f[0, 0] == -f[1, 0]
+
+
+def test_invalid_cutoffs_rejected():
+    cells = (4, 4, 4)
+    x, v, ids = _state(cells, 3.0, 37)
+    p = oracle.make_params()
+    t = inputs.species_types(len(x), [0.5, 0.5], seed=37)
+    ok_a, ok_g = np.full((2, 2), 25.0), np.full((2, 2), 4.5)
+    for rc_tab in ([[1.0, 0.8], [0.7, 1.0]], [[1.0, 1.2], [1.2, 1.0]], [[1.0, 0.0], [0.0, 1.0]]):
+        with pytest.raises(RuntimeError):
+            oracle.forces(x, v, ids, cells, oracle.with_species(p, t, ok_a, ok_g, rc_tab), 0, 0)
+
+
+@pytest.mark.slow
+def test_mixture_mean_field_pressure_with_cutoffs():
+    cells = (6, 6, 6)
+    x, v, ids = _state(cells, 3.0, 38)
+    types = inputs.species_types(len(x), [0.5, 0.5], seed=38)
+    a_tab = np.array([[0.3, 0.2], [0.2, 0.1]])
+    rc_tab = np.array([[1.0, 0.7], [0.7, 0.85]])
+    p = oracle.make_params(a=0.0, gamma=4.5, kT=1.0, dt=0.01)
+    q = oracle.with_species(p, types, a_tab, np.full((2, 2), 4.5), rc_tab)
+    diag, _, _, _ = oracle.step(x, v, ids, cells, q, 38, 0, 3000)
+    vol = float(np.prod(cells))
+    rho_s = np.array([(types == s).sum() for s in range(2)]) / vol
+    pex = diag["pressure"][500:].mean() - rho_s.sum() * diag["kT_centred"][500:].mean()
+    mean_field = math.pi / 30.0 * float(rho_s @ (a_tab * rc_tab ** 4) @ rho_s)
+    assert abs(pex - mean_field) < 0.05 * mean_field, (pex, mean_field)
+
+
+@pytest.mark.slow
+def test_equipartition_with_pair_cutoffs():
+    cells = (8, 8, 8)
+    x, v, ids = _state(cells, 3.0, 39)
+    types = inputs.species_types(len(x), [0.5, 0.5], seed=39)
+    p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    q = oracle.with_species(p, types, np.full((2, 2), 25.0), [[4.5, 9.0], [9.0, 4.5]], [[1.0, 0.8], [0.8, 0.9]])
+    kt = _species_kT(x, v, ids, cells, q, types, 39, 5000, 5, 1000)
+    m = kt.mean(axis=0)
+    assert np.all(np.abs(m - 1.0) < 0.015), m
