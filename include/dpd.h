@@ -175,18 +175,22 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
 int dpd_set_params(dpd_box box, const dpd_params* params);
 
 /* Species: several fluids in one box, each pair of species with its own
- * conservative amplitude and dissipative coefficient (fluids of different
- * viscosity side by side, Sec. 2.3, Sec. 5.2 and Sec. 5.3 of the paper; a
- * cross entry gamma = 0 couples two fluids through the conservative force
- * alone).  a_tab and gamma_tab are host arrays of ntypes x ntypes doubles,
- * row-major, symmetric, finite, gamma >= 0; the pair (s, t) then takes
- * a = a_tab[s][t], gamma = gamma_tab[s][t] and sigma = sqrt(2 gamma kT),
- * and dpd_params.a / .gamma are ignored.  kT, dt, the mass and the kernels
- * stay shared.  ntypes in 1..DPD_MAX_TYPES; ntypes = 0 returns to one
- * species described by dpd_params.  DPD_EINVAL if a particle already has a
- * species >= ntypes.  The tables are copied; may be called at any time
- * (also between steps) and take effect from the next step. */
-int dpd_set_species(dpd_box box, int32_t ntypes, const double* a_tab, const double* gamma_tab);
+ * conservative amplitude, dissipative coefficient and cutoff (fluids of
+ * different viscosity side by side, Sec. 2.3, Sec. 5.2 and Sec. 5.3 of the
+ * paper; a cross entry gamma = 0 couples two fluids through the
+ * conservative force alone; several cutoffs, Sec. 3.1).  a_tab, gamma_tab
+ * and rc_tab are host arrays of ntypes x ntypes doubles, row-major,
+ * symmetric, finite, gamma >= 0, 1/16 <= rc <= 1 (the cell edge; rc_tab
+ * NULL: every cutoff 1); the pair (s, t) then takes a = a_tab[s][t],
+ * gamma = gamma_tab[s][t], sigma = sqrt(2 gamma kT) and the cutoff
+ * r_c = rc_tab[s][t] with w = 1 - r / r_c, and dpd_params.a / .gamma are
+ * ignored.  kT, dt, the mass and the kernel exponent stay shared.  ntypes in
+ * 1..DPD_MAX_TYPES; ntypes = 0 returns to one species described by
+ * dpd_params.  DPD_EINVAL if a particle already has a species >= ntypes.
+ * The tables are copied; may be called at any time (also between steps) and
+ * take effect from the next step. */
+int dpd_set_species(dpd_box box, int32_t ntypes, const double* a_tab, const double* gamma_tab,
+                    const double* rc_tab);
 
 /* Number of species set by dpd_set_species (0: one species from params). */
 int dpd_get_species(dpd_box box, int32_t* ntypes);

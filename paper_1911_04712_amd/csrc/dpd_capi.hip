@@ -144,6 +144,7 @@ struct dpd_box_s {
     int ntypes = 0;
     double a_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
     double g_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
+    double rc_tab[dpd::kMaxTypes * dpd::kMaxTypes] = {};
     int max_type = 0;          // largest species assigned since the state was loaded
     int n_frozen = 0;          // frozen wall particles of the current state
     double rho_occ = 0.0;      // particles per occupied cell of the loaded state (0: use n / nc)
@@ -176,13 +177,15 @@ dpd::ForceConst force_const(const dpd_box_s* b)
     auto sig_rdt = [&](double g) { return (float)(std::sqrt(2.0 * g * p.kT) / std::sqrt(p.dt)); };
     fc.pc.k0 = (uint32_t)b->seed;
     fc.pc.k1 = (uint32_t)(b->seed >> 32);
-    fc.ntypes = b->ntypes;
+    // ntypes > 1 switches the kernels to the pair table: several species, or
+    // one species with a cutoff of its own below the cell edge
+    fc.ntypes = (b->ntypes == 1 && b->rc_tab[0] != 1.0) ? 2 : b->ntypes;
     if (b->ntypes >= 1) {
         constexpr int M = dpd::kMaxTypes;
         for (int u = 0; u < b->ntypes; ++u)
             for (int v = 0; v < b->ntypes; ++v) {
-                const double a = b->a_tab[u * M + v], g = b->g_tab[u * M + v];
-                fc.tab[u * M + v] = make_float4((float)a, (float)g, sig_rdt(g), 0.0f);
+                const double a = b->a_tab[u * M + v], g = b->g_tab[u * M + v], rc = b->rc_tab[u * M + v];
+                fc.tab[u * M + v] = make_float4((float)a, (float)g, sig_rdt(g), (float)(1.0 / rc));
             }
         fc.pc.a = fc.tab[0].x;         // one species: the table's only entry, on the plain path
         fc.pc.gamma = fc.tab[0].y;
@@ -192,9 +195,10 @@ dpd::ForceConst force_const(const dpd_box_s* b)
         fc.pc.gamma = (float)p.gamma;
         fc.pc.sig_rdt = sig_rdt(p.gamma);
     }
-    if (b->ntypes <= 1)                // every entry is the one species (a batch may run this box on
-        for (auto& e : fc.tab)         // the species kernel, whatever its particles' .w hold)
-            e = make_float4(fc.pc.a, fc.pc.gamma, fc.pc.sig_rdt, 0.0f);
+    if (b->ntypes <= 1) {              // every entry is the one species (a batch may run this box on
+        const float4 e0 = b->ntypes == 1 ? fc.tab[0] : make_float4(fc.pc.a, fc.pc.gamma, fc.pc.sig_rdt, 1.0f);
+        for (auto& e : fc.tab) e = e0; // the table path, whatever its particles' .w hold)
+    }
     fc.pc.kgen = (p.kexp != 0.0 && p.kexp != 1.0) ? 1 : 0;
     fc.pc.kexp = fc.pc.kgen ? (float)p.kexp : 1.0f;
     for (int k = 0; k < 3; ++k) {
@@ -476,7 +480,7 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
     return push_desc(b);
 }
 
-int dpd_set_species(dpd_box b, int32_t ntypes, const double* a_tab, const double* gamma_tab)
+int dpd_set_species(dpd_box b, int32_t ntypes, const double* a_tab, const double* gamma_tab, const double* rc_tab)
 {
     if (!b) return fail(DPD_EINVAL, "dpd_set_species: null box");
     if (ntypes < 0 || ntypes > dpd::kMaxTypes) return fail(DPD_EINVAL, "dpd_set_species: ntypes must be in 0..%d", dpd::kMaxTypes);
@@ -490,15 +494,23 @@ int dpd_set_species(dpd_box b, int32_t ntypes, const double* a_tab, const double
                 return fail(DPD_EINVAL, "dpd_set_species: entry (%d, %d) not finite, gamma < 0 or out of range", u, v);
             if (a != a_tab[v * ntypes + u] || g != gamma_tab[v * ntypes + u])
                 return fail(DPD_EINVAL, "dpd_set_species: tables must be symmetric (entry (%d, %d))", u, v);
+            if (rc_tab) {
+                const double c = rc_tab[u * ntypes + v];
+                if (!(c >= 1.0 / 16.0 && c <= 1.0) || c != rc_tab[v * ntypes + u])
+                    return fail(DPD_EINVAL, "dpd_set_species: cutoff (%d, %d) must be symmetric and in [1/16, 1]", u, v);
+            }
         }
     constexpr int M = dpd::kMaxTypes;
-    for (int k = 0; k < M * M; ++k) b->a_tab[k] = b->g_tab[k] = 0.0;
+    for (int k = 0; k < M * M; ++k) {
+        b->a_tab[k] = b->g_tab[k] = 0.0;
+        b->rc_tab[k] = 1.0;
+    }
     for (int u = 0; u < ntypes; ++u)
         for (int v = 0; v < ntypes; ++v) {
             b->a_tab[u * M + v] = a_tab[u * ntypes + v];
             b->g_tab[u * M + v] = gamma_tab[u * ntypes + v];
+            if (rc_tab) b->rc_tab[u * M + v] = rc_tab[u * ntypes + v];
         }
-    if ((b->ntypes > 1) != (ntypes > 1)) b->graph_dirty = true;   // another force kernel
     b->ntypes = ntypes;
     return push_desc(b);
 }

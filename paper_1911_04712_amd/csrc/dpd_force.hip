@@ -59,15 +59,28 @@ __device__ __forceinline__ float4 finish_force(long long ax, long long ay, long 
 // Pair (i, j) given both particles' (image-shifted) positions and
 // velocities: adds the fixed-point force on i to a[0..2].  Returns false if
 // the force is outside the fixed-point range (reported as non-finite).
+// kCut: the pair has its own cutoff r_c <= 1; the displacement is measured
+// in units of it (inv_rc = 1 / r_c: w = 1 - r / r_c, and the direction and
+// the velocity projection do not change), and pairs beyond it add nothing.
+// The negated displacement scales to the negated value, so F_ji = -F_ij
+// still holds bit for bit; inv_rc = 1 leaves every bit as it is.
+template <bool kCut = false>
 __device__ __forceinline__ bool pair_fx(float4 pi, float4 vi, float4 pj, float4 vj, uint32_t step, const PairConst& pc,
-                                        long long& fx, long long& fy, long long& fz)
+                                        long long& fx, long long& fy, long long& fz, float inv_rc = 1.0f)
 {
-    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    if constexpr (kCut) {
+        dx *= inv_rc;
+        dy *= inv_rc;
+        dz *= inv_rc;
+    }
     const float r2 = dist2(dx, dy, dz);
     const float xi = pair_xi(__float_as_uint(pi.w), __float_as_uint(pj.w), step, pc.k0, pc.k1);
     float rinv;
     const float fs = pair_scalar(r2, dx, dy, dz, vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, rinv, xi, pc);
-    const bool live = r2 > 0.0f;        // coincident particles exert no force on each other
+    // coincident particles exert no force on each other; with a pair cutoff
+    // the candidate test (r < 1) lets through pairs beyond it
+    const bool live = r2 > 0.0f && (!kCut || r2 < 1.0f);
     const float Fx = live ? fs * (dx * rinv) : 0.0f, Fy = live ? fs * (dy * rinv) : 0.0f,
                 Fz = live ? fs * (dz * rinv) : 0.0f;
     if (!(fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit)) {
@@ -120,7 +133,7 @@ __device__ float4 gather_force_one(int i, const float4* __restrict__ pos, const 
                         pc.a = c.x;
                         pc.gamma = c.y;
                         pc.sig_rdt = c.z;
-                        bad |= !pair_fx(pi, vi, pj, vj, step, pc, fx, fy, fz);
+                        bad |= !pair_fx<true>(pi, vi, pj, vj, step, pc, fx, fy, fz, c.w);
                     } else {
                         bad |= !pair_fx(pi, vi, pj, vj, step, fc.pc, fx, fy, fz);
                     }
@@ -193,7 +206,7 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
         q.a = c.x;
         q.gamma = c.y;
         q.sig_rdt = c.z;
-        bad |= !pair_fx(sp[a], va, sp[b], vb, step, q, fx, fy, fz);
+        bad |= !pair_fx<true>(sp[a], va, sp[b], vb, step, q, fx, fy, fz, c.w);
         ia = wa & 0xffffff;
         ib = (wb << 8) >> 8;
     } else {

@@ -83,8 +83,8 @@ struct ForceConst {
     int flow_axis, grad_axis;
     float half_grad;   // L_grad / 2
     int body_uniform;  // 1: +body_f everywhere, 0: the two halves of Eq. 11
-    int ntypes;        // species; > 1: each pair takes (a, gamma, sigma / sqrt(dt)) from tab
-    float4 tab[kMaxTypes * kMaxTypes];   // [s * kMaxTypes + t], symmetric; unused entries 0
+    int ntypes;        // species; > 1: each pair takes (a, gamma, sigma / sqrt(dt), 1 / r_c) from tab
+    float4 tab[kMaxTypes * kMaxTypes];   // [s * kMaxTypes + t], symmetric
 };
 
 // Table entry of the species pair (s, t).  The species sit in the .w of the

@@ -480,8 +480,13 @@ __global__ __launch_bounds__(kBlock) void k_virial(const BoxDesc* __restrict__ d
                         const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                         if (!(r2 < 1.0) || r2 == 0.0) continue;
                         const double r = sqrt(r2);
-                        const float a = species ? fc.tab[species_pair(ti, __float_as_int(vel[j].w))].x : fc.pc.a;
-                        acc += 0.5 * (double)a * (1.0 - r) * r;
+                        if (species) {          // the pair's a and cutoff
+                            const float4 c = fc.tab[species_pair(ti, __float_as_int(vel[j].w))];
+                            const double w = 1.0 - r * (double)c.w;
+                            if (w > 0.0) acc += 0.5 * (double)c.x * w * r;
+                        } else {
+                            acc += 0.5 * (double)fc.pc.a * (1.0 - r) * r;
+                        }
                     }
                 }
             }

@@ -102,7 +102,7 @@ SIGNATURES = {
     "dpd_server_clock": ([_VP], ctypes.c_double),
     "dpd_server_destroy": ([_VP], ctypes.c_int),
     "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
-    "dpd_set_species": ([_VP, ctypes.c_int32, _VP, _VP], ctypes.c_int),
+    "dpd_set_species": ([_VP, ctypes.c_int32, _VP, _VP, _VP], ctypes.c_int),
     "dpd_get_species": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_set_types": ([_VP, _VP], ctypes.c_int),
     "dpd_set_frozen": ([_VP, _VP], ctypes.c_int),
@@ -266,17 +266,22 @@ class Box:
             raise ValueError("pos and vel must both be host arrays or both device tensors")
         _check(lib().dpd_set_state(self._h, pp, vp, wp))
 
-    def set_species(self, a_tab=None, gamma_tab=None):
-        """Per species-pair a and gamma (symmetric ntypes x ntypes tables);
-        no tables returns to the single species of the params."""
+    def set_species(self, a_tab=None, gamma_tab=None, rc_tab=None):
+        """Per species-pair a, gamma and cutoff (symmetric ntypes x ntypes
+        tables; no rc_tab: every cutoff 1); no tables returns to the single
+        species of the params."""
         if a_tab is None:
-            _check(lib().dpd_set_species(self._h, 0, None, None))
+            _check(lib().dpd_set_species(self._h, 0, None, None, None))
             return
         a = np.ascontiguousarray(a_tab, dtype=np.float64)
         g = np.ascontiguousarray(gamma_tab, dtype=np.float64)
         if a.ndim != 2 or a.shape[0] != a.shape[1] or g.shape != a.shape:
             raise ValueError("a_tab and gamma_tab must be square tables of one shape")
-        _check(lib().dpd_set_species(self._h, a.shape[0], a.ctypes.data, g.ctypes.data))
+        c = None if rc_tab is None else np.ascontiguousarray(rc_tab, dtype=np.float64)
+        if c is not None and c.shape != a.shape:
+            raise ValueError("rc_tab must have the shape of a_tab")
+        _check(lib().dpd_set_species(self._h, a.shape[0], a.ctypes.data, g.ctypes.data,
+                                     None if c is None else c.ctypes.data))
 
     def get_species(self):
         nt = ctypes.c_int32()

@@ -217,3 +217,74 @@ def test_species_errors():
     b.set_species([[25.0]], [[4.5]])
     np.testing.assert_array_equal(b.get_types(), np.zeros(len(pos), dtype=np.int32))
     b.close()
+
+
+RC3 = np.array([[1.0, 0.8, 0.9], [0.8, 0.6, 0.7], [0.9, 0.7, 1.0]])
+
+
+@pytest.mark.parametrize("cells,rho,kexp", [((8, 7, 9), 3.0, 1.0), ((9, 6, 5), 8.0, 1.0), ((7, 7, 7), 4.0, 0.25)])
+def test_pair_cutoffs_match_oracle(cells, rho, kexp):
+    # a cutoff per species pair (Sec. 3.1 keeps several): w = 1 - r / r_c
+    pos, vel = inputs.uniform_state(cells, density=rho, seed=47)
+    types = inputs.species_types(len(pos), [0.4, 0.3, 0.3], seed=47)
+    p = dpd.make_params(kexp=kexp, dt=0.005, flags=dpd.FLAG_VIRIAL)
+    out = []
+    for flags in (dpd.FLAG_VIRIAL, dpd.FLAG_REFERENCE_FORCE):
+        p.flags = flags
+        b = dpd.Box(cells, len(pos), params=p, seed=47)
+        b.set_state(pos, vel)
+        b.set_species(A3, G3, RC3)
+        b.set_types(types)
+        b.step(1)
+        out.append((b.read(dpd.FORCE), b.stats()["virial"]))
+        b.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])           # tile kernel = gather kernel
+    ids = np.arange(len(pos), dtype=np.uint32)
+    q = oracle.with_species(_orc_params(p), types, A3, G3, RC3)
+    fo, so, vo = oracle.forces(pos, vel, ids, cells, q, 0, 47)
+    _force_check(out[0][0], fo, so, f"cutoffs {cells} rho={rho} k={kexp}")
+    assert out[0][1] == pytest.approx(vo, rel=1e-5)
+
+
+def test_unit_cutoffs_are_the_same_bits():
+    cells = (9, 8, 7)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=48)
+    types = inputs.species_types(len(pos), [0.4, 0.3, 0.3], seed=48)
+    out = []
+    for rc in (None, np.ones((3, 3))):
+        b = dpd.Box(cells, len(pos), params=dpd.make_params(), seed=48)
+        b.set_state(pos, vel)
+        b.set_species(A3, G3, rc)
+        b.set_types(types)
+        b.step(4)
+        out.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE)))
+        b.close()
+    for x, y in zip(*out):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_one_species_with_its_own_cutoff():
+    cells = (8, 8, 8)
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=49)
+    p = dpd.make_params(a=25.0, gamma=4.5)
+    b = dpd.Box(cells, len(pos), params=p, seed=49)
+    b.set_state(pos, vel)
+    b.set_species([[25.0]], [[4.5]], [[0.75]])
+    b.step(1)
+    f = b.read(dpd.FORCE)
+    b.close()
+    ids = np.arange(len(pos), dtype=np.uint32)
+    q = _orc_params(p)
+    q.rc = 0.75                     # the oracle's one-species cutoff
+    fo, so, _ = oracle.forces(pos, vel, ids, cells, q, 0, 49)
+    _force_check(f, fo, so, "one species, r_c = 0.75")
+
+
+def test_cutoff_errors():
+    b = dpd.Box((5, 5, 5), 375, params=dpd.make_params(), seed=50)
+    a, g = np.full((2, 2), 25.0), np.full((2, 2), 4.5)
+    for rc in ([[1.0, 1.2], [1.2, 1.0]], [[1.0, 0.8], [0.7, 1.0]], [[1.0, 0.01], [0.01, 1.0]]):
+        with pytest.raises(dpd.DPDError) as e:
+            b.set_species(a, g, rc)
+        assert e.value.code == dpd.EINVAL
+    b.close()
