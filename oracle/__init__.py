@@ -23,7 +23,8 @@ class Params(ctypes.Structure):
                 ("g_tab", ctypes.POINTER(ctypes.c_double)),
                 ("body_uniform", ctypes.c_int32), ("wall_kind", ctypes.c_int32), ("wall_h", ctypes.c_double),
                 ("frozen", ctypes.POINTER(ctypes.c_uint8)), ("rc", ctypes.c_double),
-                ("rc_tab", ctypes.POINTER(ctypes.c_double))]
+                ("rc_tab", ctypes.POINTER(ctypes.c_double)), ("wall_r_in", ctypes.c_double),
+                ("omega_in", ctypes.c_double), ("omega_out", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
@@ -66,6 +67,7 @@ def lib():
                                ctypes.POINTER(Diag), dp, dp, dp]
         L.orc_sdf.argtypes = [dp, i32p, ctypes.POINTER(Params)]
         L.orc_sdf.restype = ctypes.c_double
+        L.orc_wall_velocity.argtypes = [dp, i32p, ctypes.POINTER(Params), dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -101,15 +103,17 @@ def with_species(params, types, a_tab, g_tab, rc_tab=None):
     return q
 
 
-def with_walls(params, kind, h, frozen=None, body_uniform=True):
+def with_walls(params, kind, h, frozen=None, body_uniform=True, r_in=0.0, omega_in=0.0, omega_out=0.0):
     """Copy of params with walls: kind 1 = two plates normal to grad_axis
     (fluid where |y - L/2| < h), 2 = a pipe of radius h along flow_axis
-    through the box centre; frozen[i] = 1 marks a wall particle.  The body
-    force becomes uniform unless body_uniform is False."""
+    through the box centre, 3 = coaxial cylinders of radii r_in < h along
+    flow_axis turning at omega_in and omega_out; frozen[i] = 1 marks a wall
+    particle.  The body force becomes uniform unless body_uniform is False."""
     q = Params()
     ctypes.pointer(q)[0] = params
     keep = list(getattr(params, "_keep", ()))
     q.wall_kind, q.wall_h, q.body_uniform = int(kind), float(h), int(bool(body_uniform))
+    q.wall_r_in, q.omega_in, q.omega_out = float(r_in), float(omega_in), float(omega_out)
     if frozen is not None:
         fz = np.ascontiguousarray(frozen, dtype=np.uint8)
         q.frozen = _p(fz, ctypes.c_uint8)
@@ -125,6 +129,18 @@ def sdf(points, cells, params):
     L = lib()
     return np.array([L.orc_sdf(_p(pts[k], ctypes.c_double), _p(c, ctypes.c_int32), ctypes.byref(params))
                      for k in range(len(pts))])
+
+
+def wall_velocity(points, cells, params):
+    """The oracle's wall velocity field at each point."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    out = np.zeros_like(pts)
+    L = lib()
+    for k in range(len(pts)):
+        L.orc_wall_velocity(_p(pts[k], ctypes.c_double), _p(c, ctypes.c_int32), ctypes.byref(params),
+                            _p(out[k], ctypes.c_double))
+    return out
 
 
 def philox4x32_10(ctr, key):

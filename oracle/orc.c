@@ -18,7 +18,8 @@
  *   - fused velocity-Verlet (kick, drift)  Sec. 3.1, time-stepping step 5
  *   - periodic Poiseuille body force ..... Sec. 4.2, Eq. (11)
  *   - walls: SDF surface, frozen particles, Sec. 2.3; bounce-back at the
- *     SDF's zero along the drift, Sec. 3.3
+ *     SDF's zero along the drift, Sec. 3.3; rotating coaxial cylinders of
+ *     the Taylor-Couette test, Sec. 4.3
  *   - several species with their own a, gamma and cutoff per pair of
  *     species (fluids of different viscosity side by side: Sec. 2.3,
  *     Sec. 5.2, Sec. 5.3; several cutoffs: Sec. 3.1); kT, dt and the mass
@@ -74,6 +75,13 @@ typedef struct {
                             0 means 1                                        */
     const double* rc_tab; /* ntypes x ntypes, symmetric: cutoff per species
                              pair (NULL: every pair at rc)                   */
+    double wall_r_in;    /* wall_kind 3: two coaxial cylinders along
+                            flow_axis through the box centre, fluid where
+                            wall_r_in < distance to the axis < wall_h     */
+    double omega_in, omega_out; /* their angular velocities about the axis
+                            (right-handed about +flow_axis); every wall has
+                            a velocity field omega x r and frozen particles
+                            carry it                                       */
 } orc_params;
 
 typedef struct {
@@ -388,22 +396,40 @@ double orc_sdf(const double* r, const int32_t cells[3], const orc_params* p)
         double y = r[p->grad_axis] - 0.5 * (double)cells[p->grad_axis];
         return fabs(y) - p->wall_h;
     }
-    if (p->wall_kind == 2) {
+    if (p->wall_kind == 2 || p->wall_kind == 3) {
         double q2 = 0.0;
         for (int k = 0; k < 3; ++k) {
             if (k == p->flow_axis) continue;
             double c = r[k] - 0.5 * (double)cells[k];
             q2 += c * c;
         }
-        return sqrt(q2) - p->wall_h;
+        double q = sqrt(q2);
+        if (p->wall_kind == 2) return q - p->wall_h;
+        return fmax(p->wall_r_in - q, q - p->wall_h);
     }
     return -1.0;
+}
+
+/* Velocity of the wall surface nearest to r: omega x (r - axis), with the
+ * inner cylinder's omega inside the mid radius and the outer one's outside
+ * (Sec. 4.3); zero for plates and pipes. */
+void orc_wall_velocity(const double* r, const int32_t cells[3], const orc_params* p, double u[3])
+{
+    u[0] = u[1] = u[2] = 0.0;
+    if (p->wall_kind != 3) return;
+    int a1 = (p->flow_axis + 1) % 3, a2 = (p->flow_axis + 2) % 3;   /* right-handed about the axis */
+    double c1 = r[a1] - 0.5 * (double)cells[a1], c2 = r[a2] - 0.5 * (double)cells[a2];
+    double q = sqrt(c1 * c1 + c2 * c2);
+    double om = q < 0.5 * (p->wall_r_in + p->wall_h) ? p->omega_in : p->omega_out;
+    u[a1] = -om * c2;
+    u[a2] = om * c1;
 }
 
 /* Bounce-back (Sec. 3.3): a particle whose drift from x0 by dx ends inside
  * the wall is placed at the collision point, the zero of the SDF along the
  * drift (found by bisection; the fluid-side end of the final bracket), and
- * its velocity is reversed (the walls are at rest).  Returns 1 on a bounce. */
+ * its velocity is reversed in the frame of the wall there: v -> 2 u_w - v
+ * (v -> -v for walls at rest).  Returns 1 on a bounce. */
 static int orc_bounce(const double x0[3], const double dx[3], double x[3], double v[3], const int32_t cells[3],
                       const orc_params* p)
 {
@@ -414,11 +440,32 @@ static int orc_bounce(const double x0[3], const double dx[3], double x[3], doubl
         for (int k = 0; k < 3; ++k) m[k] = x0[k] + mid * dx[k];
         if (orc_sdf(m, cells, p) > 0.0) hi = mid; else lo = mid;
     }
-    for (int k = 0; k < 3; ++k) {
-        x[k] = x0[k] + lo * dx[k];
-        v[k] = -v[k];
-    }
+    for (int k = 0; k < 3; ++k) x[k] = x0[k] + lo * dx[k];
+    double u[3];
+    orc_wall_velocity(x, cells, p, u);
+    for (int k = 0; k < 3; ++k) v[k] = 2.0 * u[k] - v[k];
     return 1;
+}
+
+/* A frozen particle of a turning cylinder turns with it: its position is
+ * rotated about the axis by omega dt each step (the surface, and so the
+ * SDF, is unchanged by the rotation) and its velocity is the wall velocity
+ * at the new position.  Frozen particles of resting walls keep position and
+ * velocity.  Moving the layer with its wall, rather than only giving it the
+ * wall's velocity, keeps the static corrugation of fixed particles from
+ * dragging the fluid back towards rest. */
+static void orc_move_frozen(double* x, double* v, const int32_t cells[3], const orc_params* p)
+{
+    if (p->wall_kind != 3) return;
+    int a1 = (p->flow_axis + 1) % 3, a2 = (p->flow_axis + 2) % 3;
+    double c1 = x[a1] - 0.5 * (double)cells[a1], c2 = x[a2] - 0.5 * (double)cells[a2];
+    double q = sqrt(c1 * c1 + c2 * c2);
+    double om = q < 0.5 * (p->wall_r_in + p->wall_h) ? p->omega_in : p->omega_out;
+    if (om == 0.0) return;
+    double ph = om * p->dt, cs = cos(ph), sn = sin(ph);
+    x[a1] = 0.5 * (double)cells[a1] + cs * c1 - sn * c2;
+    x[a2] = 0.5 * (double)cells[a2] + sn * c1 + cs * c2;
+    orc_wall_velocity(x, cells, p, v);
 }
 
 static int orc_check(const int32_t cells[3], const orc_params* p)
@@ -430,7 +477,8 @@ static int orc_check(const int32_t cells[3], const orc_params* p)
     if (p->flow_axis < 0 || p->flow_axis > 2 || p->grad_axis < 0 || p->grad_axis > 2) return -1;
     if (p->flow_axis == p->grad_axis) return -1;
     if (p->ntypes < 0 || p->ntypes > 64) return -1;
-    if (p->wall_kind < 0 || p->wall_kind > 2 || (p->wall_kind && !(p->wall_h > 0.0))) return -1;
+    if (p->wall_kind < 0 || p->wall_kind > 3 || (p->wall_kind && !(p->wall_h > 0.0))) return -1;
+    if (p->wall_kind == 3 && !(p->wall_r_in > 0.0 && p->wall_r_in < p->wall_h)) return -1;
     if (p->ntypes > 1) {
         if (!p->type || !p->a_tab || !p->g_tab) return -1;
         for (int s = 0; s < p->ntypes; ++s)
@@ -509,9 +557,10 @@ int orc_forces(int64_t n, const double* x, const double* v, const uint32_t* id,
  *      x^{n+1} = x^n + dt v^{n+1/2}, bounce-back off the walls (Sec. 3.3),
  *      then periodic wrap;
  *   4. momentum and KE of v^{n+1/2}.
- * Frozen wall particles (Sec. 2.3) take part in the forces only: they are
- * neither moved nor counted in the diagnostics (kT uses 3 (N_fluid - 1)
- * degrees of freedom) or the profile.
+ * Frozen wall particles (Sec. 2.3) take part in the forces, move only with
+ * their wall (a turning cylinder turns them, orc_move_frozen) and are not
+ * counted in the diagnostics (kT uses 3 (N_fluid - 1) degrees of freedom)
+ * or the profile.
  * diag (nsteps entries), prof_sum / prof_cnt (nbins, accumulated) and
  * f_last (n x 3, forces of the last step) may each be NULL. */
 int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t cells[3],
@@ -551,7 +600,10 @@ int orc_step(int64_t n, double* x, double* v, const uint32_t* id, const int32_t 
         }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            if (p->frozen && p->frozen[i]) continue;          /* wall particles stay put */
+            if (p->frozen && p->frozen[i]) {                  /* wall particles move with their wall */
+                orc_move_frozen(x + 3 * i, v + 3 * i, cells, p);
+                continue;
+            }
             double x0[3], dx[3];
             for (int k = 0; k < 3; ++k) {
                 v[3 * i + k] += p->dt * f[3 * i + k] / p->mass;

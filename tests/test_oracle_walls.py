@@ -15,7 +15,11 @@ the oracle:
   - over a long run no fluid particle is ever found inside a wall;
   - channel (plane Poiseuille) flow between frozen walls has the parabolic
     profile v = rho f (h^2 - y^2) / (2 eta) with the viscosity the periodic
-    Poiseuille measurement gives for the same fluid.
+    Poiseuille measurement gives for the same fluid;
+  - rotating coaxial cylinders (Taylor-Couette, Sec. 4.3): a crossing of
+    either cylinder lands on it with the velocity reversed in the frame of
+    that wall (v -> 2 omega x r - v), a turning cylinder's frozen layer turns
+    rigidly with it, and the azimuthal profile is A r + B / r.
 """
 import math
 
@@ -151,3 +155,103 @@ def test_channel_flow_parabola_and_viscosity():
     assert np.max(np.abs(resid)) < 0.1 * c0, (resid, c0)
     assert 0.75 < eta < 1.05, eta
     assert abs(y0 - h) < 0.5, y0           # no-slip up to a fraction of r_c
+
+
+# ---------------------------------------------------------------------------
+# rotating coaxial cylinders (Taylor-Couette, Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def _couette_params(base, frozen=None, r_in=2.0, r_out=5.0, w_in=0.0, w_out=0.3):
+    return oracle.with_walls(base, 3, r_out, frozen, body_uniform=True, r_in=r_in, omega_in=w_in, omega_out=w_out)
+
+
+@pytest.mark.parametrize("outward", [True, False])
+def test_rotating_wall_bounce_closed_form(outward):
+    cells = (4, 12, 12)                    # cylinders along x through (y, z) = (6, 6)
+    r_in, r_out, w_in, w_out = 2.0, 5.0, -0.2, 0.3
+    p = _couette_params(oracle.make_params(a=0.0, gamma=0.0, kT=0.0, dt=0.01), None, r_in, r_out, w_in, w_out)
+    ang = 0.7
+    radial = np.array([0.0, math.cos(ang), math.sin(ang)])
+    r0, R, w = (r_out - 0.004, r_out, w_out) if outward else (r_in + 0.004, r_in, w_in)
+    p0 = np.array([2.0, 6.0, 6.0]) + r0 * radial
+    vel = (1.0 if outward else -1.0) * 1.2 * radial + np.array([0.3, -0.4, 0.25])
+    x, v, ids = _two_particles(p0, vel, far=(2.0, 6.0 + 3.5 * math.cos(ang + 2), 6.0 + 3.5 * math.sin(ang + 2)))
+    oracle.step(x, v, ids, cells, p, 0, 0, 1, want_diag=False)
+    d = vel * 0.01
+    q, e = p0[1:] - 6.0, d[1:]
+    A, B, C = e @ e, 2 * q @ e, q @ q - R * R
+    roots = np.roots([A, B, C])
+    t = min(r for r in roots.real if r > 0)          # the first crossing of that circle
+    xc = p0 + t * d
+    np.testing.assert_allclose(x[0], xc, rtol=0, atol=1e-12)
+    u = np.cross([w, 0.0, 0.0], xc - np.array([xc[0], 6.0, 6.0]))    # omega x r about the axis
+    np.testing.assert_allclose(v[0], 2 * u - vel, rtol=0, atol=1e-12)
+
+
+def test_frozen_layer_turns_with_its_cylinder():
+    # a turning cylinder's frozen particles turn rigidly with it, omega dt per
+    # step about the axis, and carry omega x r; the resting cylinder's stay
+    cells = (4, 12, 12)
+    p0 = oracle.make_params(a=0.0, gamma=0.0, kT=0.0, dt=0.05)
+    x = np.array([[1.0, 6.0 + 5.5, 6.0], [1.0, 6.0, 6.0 - 1.6], [1.0, 6.0, 6.0 + 3.5], [1.0, 6.0 - 3.5, 6.0]])
+    frozen = np.array([1, 1, 0, 0], dtype=np.uint8)
+    p = _couette_params(p0, frozen, 2.0, 5.0, 0.0, 0.3)
+    v = np.zeros((4, 3))
+    v[:2] = oracle.wall_velocity(x[:2], cells, p)
+    ids = np.arange(4, dtype=np.uint32)
+    oracle.step(x, v, ids, cells, p, 0, 0, 10, want_diag=False)
+    ang = 0.3 * 0.05 * 10
+    np.testing.assert_allclose(x[0], [1.0, 6.0 + 5.5 * math.cos(ang), 6.0 + 5.5 * math.sin(ang)], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v[0], np.cross([0.3, 0.0, 0.0], x[0] - [1.0, 6.0, 6.0]), rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(x[1], [1.0, 6.0, 6.0 - 1.6])          # inner cylinder at rest
+    np.testing.assert_array_equal(v[1], 0.0)
+
+
+def _annulus_state(cells, rho, params, seed, equil_steps=300):
+    """Equilibrated fluid cut into an annulus: within r_c behind either
+    cylinder frozen, carrying the wall's velocity; farther out dropped."""
+    pos, vel = inputs.uniform_state(cells, density=rho, seed=seed)
+    x, v = pos.astype(np.float64), vel.astype(np.float64)
+    ids = np.arange(len(x), dtype=np.uint32)
+    free = oracle.make_params(a=params.a, gamma=params.gamma, kT=params.kT, dt=params.dt)
+    oracle.step(x, v, ids, cells, free, seed, 0, equil_steps, want_diag=False)
+    s = oracle.sdf(x, cells, params)
+    keep = s <= 1.0
+    x, v = x[keep].copy(), v[keep].copy()
+    frozen = (s[keep] > 0.0).astype(np.uint8)
+    v[frozen == 1] = oracle.wall_velocity(x[frozen == 1], cells, params)
+    return x, v, frozen
+
+
+@pytest.mark.slow
+def test_taylor_couette_profile():
+    """Inner cylinder at rest, outer turning (the paper's Sec. 4.3 setting):
+    the azimuthal velocity follows A r + B / r with A, B from the radii and
+    angular velocities (the general form of Eq. 12)."""
+    cells, rho = (4, 18, 18), 3.0
+    r_in, r_out, w_out = 3.0, 7.5, 0.06
+    base = oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    geo = _couette_params(base, None, r_in, r_out, 0.0, w_out)
+    x, v, frozen = _annulus_state(cells, rho, geo, 54)
+    p = _couette_params(base, frozen, r_in, r_out, 0.0, w_out)
+    ids = np.arange(len(x), dtype=np.uint32)
+    oracle.step(x, v, ids, cells, p, 54, 0, 3000, want_diag=False)          # spin-up, ~5 relaxation times
+    edges = np.linspace(r_in, r_out, 10)
+    acc, cnt = np.zeros(9), np.zeros(9)
+    fl = frozen == 0
+    for k in range(80):
+        oracle.step(x, v, ids, cells, p, 54, 3000 + 100 * k, 100, want_diag=False)
+        c = x[fl][:, 1:] - 9.0
+        r = np.hypot(c[:, 0], c[:, 1])
+        vt = (c[:, 0] * v[fl][:, 2] - c[:, 1] * v[fl][:, 1]) / r
+        b = np.clip(np.searchsorted(edges, r) - 1, 0, 8)
+        np.add.at(acc, b, vt)
+        np.add.at(cnt, b, 1)
+    rm = 0.5 * (edges[1:] + edges[:-1])
+    prof = acc / cnt
+    A = w_out * r_out ** 2 / (r_out ** 2 - r_in ** 2)
+    B = -w_out * r_in ** 2 * r_out ** 2 / (r_out ** 2 - r_in ** 2)
+    want = A * rm + B / rm
+    print("taylor-couette", np.round(prof, 4), np.round(want, 4))
+    inner = (rm > r_in + 0.6) & (rm < r_out - 0.6)
+    assert np.max(np.abs(prof[inner] - want[inner])) < 0.08 * w_out * r_out
