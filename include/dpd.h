@@ -95,8 +95,12 @@ enum {
 enum {
     DPD_WALL_NONE = 0,
     DPD_WALL_PLATES = 1,  /* two plates normal to grad_axis: sdf = |y - L_y/2| - wall_h   */
-    DPD_WALL_PIPE = 2     /* a pipe along flow_axis through the box centre:
+    DPD_WALL_PIPE = 2,    /* a pipe along flow_axis through the box centre:
                              sdf = (distance to the axis) - wall_h                      */
+    DPD_WALL_CYLINDERS = 3 /* two coaxial cylinders along flow_axis through the box
+                             centre (Taylor-Couette, Sec. 4.3): sdf = max(wall_r_in - q,
+                             q - wall_h), q the distance to the axis; the inner one
+                             turns at omega_in, the outer at omega_out             */
 };
 
 typedef struct dpd_box_s* dpd_box;
@@ -134,9 +138,17 @@ typedef struct {
                              sdf's zero along the drift, with its velocity reversed
                              (bounce-back, Sec. 3.3)                               */
     int32_t reserved2;    /* must be 0                                             */
-    double wall_h;        /* plate half-gap or pipe radius; the wall and its frozen
-                             layer (thickness r_c = 1) must fit inside the box:
-                             wall_h + 1 < L/2 on every axis the sdf depends on     */
+    double wall_h;        /* plate half-gap, pipe radius or outer cylinder radius; the
+                             wall and its frozen layer (thickness r_c = 1) must fit
+                             inside the box: wall_h + 1 < L/2 on every axis the sdf
+                             depends on                                            */
+    double wall_r_in;     /* DPD_WALL_CYLINDERS: inner radius, 0 < wall_r_in < wall_h */
+    double omega_in;      /* DPD_WALL_CYLINDERS: angular velocities of the inner and   */
+    double omega_out;     /* outer cylinder, right-handed about +flow_axis.  A wall's
+                             velocity is omega x r; a bounce reverses the velocity in
+                             the frame of the wall (v -> 2 u_wall - v), and a turning
+                             cylinder's frozen particles turn rigidly with it by
+                             omega dt per step, carrying its velocity               */
 } dpd_params;
 
 /* Diagnostics, all reduced in FP64 on the GPU in a fixed order.
@@ -207,8 +219,9 @@ int dpd_get_types(dpd_box box, int32_t* type_host);
 
 /* Frozen wall particles (Sec. 2.3): frozen_host[i] != 0 marks particle id i
  * (host array of n bytes) as part of a wall's frozen layer.  Frozen
- * particles take part in every pair force but never move (their velocity is
- * set to 0, the walls being at rest), and are left out of the momentum,
+ * particles take part in every pair force but move only with their wall
+ * (their velocity is set to the wall's: 0 for plates and pipes, omega x r
+ * for a turning cylinder, which turns them), and are left out of the momentum,
  * kinetic energy, kT (3 (N_fluid - 1) degrees of freedom) and flow profile.
  * dpd_set_state and dpd_init_random clear the marks.  DPD_ESTATE without a
  * state; DPD_EINVAL if fewer than 2 particles stay free.  Synchronises. */

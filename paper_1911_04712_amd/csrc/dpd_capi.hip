@@ -236,6 +236,13 @@ dpd::StepConst step_const(const dpd_box_s* b)
     sc.wall_kind = p.wall_kind;
     sc.wall_h = (float)p.wall_h;
     for (int k = 0; k < 3; ++k) sc.centre[k] = 0.5f * b->L[k];
+    sc.wall_r_in = (float)p.wall_r_in;
+    const double om[2] = {p.omega_in, p.omega_out};
+    for (int c = 0; c < 2; ++c) {
+        sc.omega[c] = (float)om[c];
+        sc.rot[c][0] = (float)std::cos(om[c] * p.dt);
+        sc.rot[c][1] = (float)std::sin(om[c] * p.dt);
+    }
     const double vol = (double)b->cells[0] * b->cells[1] * b->cells[2];
     sc.inv_vol = 1.0 / vol;
     sc.rho = (double)b->n / vol;
@@ -457,8 +464,12 @@ int dpd_set_params(dpd_box b, const dpd_params* p)
         return fail(DPD_EINVAL, "dpd_set_params: profile_bins must be in [0, %d]", dpd::kProfileMaxBins);
     if (p->flags & ~(DPD_FLAG_VIRIAL | DPD_FLAG_REFERENCE_FORCE | DPD_FLAG_BODY_UNIFORM))
         return fail(DPD_EINVAL, "dpd_set_params: unknown flags");
-    if (p->wall_kind < DPD_WALL_NONE || p->wall_kind > DPD_WALL_PIPE || p->reserved2 != 0)
+    if (p->wall_kind < DPD_WALL_NONE || p->wall_kind > DPD_WALL_CYLINDERS || p->reserved2 != 0)
         return fail(DPD_EINVAL, "dpd_set_params: wall_kind must be a DPD_WALL_* value and reserved2 0");
+    if (!std::isfinite(p->wall_r_in) || !std::isfinite(p->omega_in) || !std::isfinite(p->omega_out))
+        return fail(DPD_EINVAL, "dpd_set_params: non-finite cylinder parameter");
+    if (p->wall_kind == DPD_WALL_CYLINDERS && !(p->wall_r_in > 0.0 && p->wall_r_in < p->wall_h))
+        return fail(DPD_EINVAL, "dpd_set_params: cylinders need 0 < wall_r_in < wall_h");
     if (p->wall_kind != DPD_WALL_NONE) {
         if (!std::isfinite(p->wall_h) || !(p->wall_h > 0.0))
             return fail(DPD_EINVAL, "dpd_set_params: wall_h must be finite and > 0");
@@ -569,9 +580,9 @@ int dpd_set_frozen(dpd_box b, const uint8_t* frozen_host)
     const dpd::BoxDesc& d = b->hd;
     unsigned char* staged = (unsigned char*)b->out;
     HIPCHK(hipMemcpyAsync(staged, frozen_host, (size_t)b->n, hipMemcpyHostToDevice, b->stream));
-    HIPCHK(dpd::launch_set_frozen(d.pos_a, d.vel_a, b->n, staged, b->stream));
+    HIPCHK(dpd::launch_set_frozen(d.pos_a, d.vel_a, b->n, staged, d.sc, b->stream));
     if (b->binned || b->have_force)     // pos_b / vel_b hold a copy of the state in cell order
-        HIPCHK(dpd::launch_set_frozen(d.pos_b, d.vel_b, b->n, staged, b->stream));
+        HIPCHK(dpd::launch_set_frozen(d.pos_b, d.vel_b, b->n, staged, d.sc, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     b->n_frozen = nf;
     return push_desc(b);                // degrees of freedom of kT

@@ -60,8 +60,11 @@ struct StepConst {
     double inv_vol;
     double rho;
     int wall_kind;     // DPD_WALL_*
-    float wall_h;      // plate half-gap or pipe radius
+    float wall_h;      // plate half-gap, pipe radius or outer cylinder radius
     float centre[3];   // L / 2
+    float wall_r_in;   // inner cylinder radius
+    float omega[2];    // angular velocities of the inner and outer cylinder
+    float rot[2][2];   // (cos, sin) of omega dt: the per-step turn of each cylinder's frozen layer
 };
 
 // Signed distance to the wall surface: negative in the fluid.
@@ -72,7 +75,41 @@ __device__ __forceinline__ float wall_sdf(float x, float y, float z, const StepC
     float q2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) q2 += k == sc.flow_axis ? 0.0f : r[k] * r[k];
-    return sqrtf(q2) - sc.wall_h;
+    const float q = sqrtf(q2);
+    return sc.wall_kind == 2 ? q - sc.wall_h : fmaxf(sc.wall_r_in - q, q - sc.wall_h);
+}
+
+// Offsets (c1, c2) of a point from the cylinders' axis along the two axes
+// after flow_axis (right-handed about it), and which cylinder it belongs to
+// (0 inner, 1 outer).  Selects, not indexed arrays, keep it in registers.
+__device__ __forceinline__ float pick3(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ __forceinline__ int cylinder_of(float x, float y, float z, const StepConst& sc, float& c1, float& c2)
+{
+    const float rx = x - sc.centre[0], ry = y - sc.centre[1], rz = z - sc.centre[2];
+    const int a1 = sc.flow_axis == 2 ? 0 : sc.flow_axis + 1;
+    const int a2 = sc.flow_axis == 0 ? 2 : sc.flow_axis - 1;
+    c1 = pick3(a1, rx, ry, rz);
+    c2 = pick3(a2, rx, ry, rz);
+    return sqrtf(c1 * c1 + c2 * c2) < 0.5f * (sc.wall_r_in + sc.wall_h) ? 0 : 1;
+}
+
+// Components along x, y, z of the vector (0 along flow_axis, c1, c2).
+__device__ __forceinline__ float3 from_axes(const StepConst& sc, float c1, float c2)
+{
+    const int a1 = sc.flow_axis == 2 ? 0 : sc.flow_axis + 1;
+    return make_float3(a1 == 0 ? c1 : (sc.flow_axis == 1 ? c2 : 0.0f),
+                       a1 == 1 ? c1 : (sc.flow_axis == 2 ? c2 : 0.0f),
+                       a1 == 2 ? c1 : (sc.flow_axis == 0 ? c2 : 0.0f));
+}
+
+// Velocity of the wall at a point: omega x r for the cylinders, else 0.
+__device__ __forceinline__ float3 wall_velocity(float x, float y, float z, const StepConst& sc)
+{
+    if (sc.wall_kind != 3) return make_float3(0.0f, 0.0f, 0.0f);
+    float c1, c2;
+    const float om = sc.omega[cylinder_of(x, y, z, sc, c1, c2)];
+    return from_axes(sc, -om * c2, om * c1);
 }
 
 struct ForceConst {
@@ -184,7 +221,8 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
 hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s);
 hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* type_by_id, hipStream_t s);
 // frozen marks by id <-> the frozen bit of vel[i].w (frozen velocities set to 0)
-hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id, hipStream_t s);
+hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id,
+                             const StepConst& sc, hipStream_t s);
 hipError_t launch_get_frozen(const float4* pos, const float4* vel, int n, unsigned char* frozen_by_id, hipStream_t s);
 hipError_t launch_wall_sdf(const float4* pos, int n, const StepConst& sc, float* sdf_by_id, hipStream_t s);
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);

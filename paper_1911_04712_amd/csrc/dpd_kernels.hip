@@ -245,14 +245,16 @@ __global__ void k_get_types(const float4* __restrict__ pos, const float4* __rest
 }
 
 __global__ void k_set_frozen(const float4* __restrict__ pos, float4* __restrict__ vel, int n,
-                             const unsigned char* __restrict__ frozen_by_id)
+                             const unsigned char* __restrict__ frozen_by_id, StepConst sc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const float4 p = pos[i];
     float4 v = vel[i];
     const int w = __float_as_int(v.w) & ~kFrozenBit;
-    if (frozen_by_id[__float_as_int(pos[i].w)]) {
-        v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(w | kFrozenBit));   // walls at rest
+    if (frozen_by_id[__float_as_int(p.w)]) {
+        const float3 u = wall_velocity(p.x, p.y, p.z, sc);         // the wall's own velocity
+        v = make_float4(u.x, u.y, u.z, __int_as_float(w | kFrozenBit));
     } else {
         v.w = __int_as_float(w);
     }
@@ -289,10 +291,12 @@ hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* ty
     return hipGetLastError();
 }
 
-hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id, hipStream_t s)
+hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsigned char* frozen_by_id,
+                             const StepConst& sc, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_set_frozen, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, frozen_by_id);
+    hipLaunchKernelGGL(k_set_frozen, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, vel, n, frozen_by_id,
+                       sc);
     return hipGetLastError();
 }
 
@@ -554,6 +558,21 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
         float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
               nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
+        if (kWalls && frozen && sc.wall_kind == 3) {
+            // a turning cylinder turns its frozen layer rigidly by omega dt
+            // about the axis; the particle carries the wall velocity there
+            float c1, c2;
+            const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
+            if (sc.omega[cyl] != 0.0f) {
+                const float cs = sc.rot[cyl][0], sn = sc.rot[cyl][1];
+                const float3 d = from_axes(sc, fmaf(cs, c1, -sn * c2) - c1, fmaf(sn, c1, cs * c2) - c2);
+                nx = x.x + d.x;
+                ny = x.y + d.y;
+                nz = x.z + d.z;
+                const float3 u = wall_velocity(nx, ny, nz, sc);
+                vx = u.x; vy = u.y; vz = u.z;
+            }
+        }
         const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) &&
                          isfinite(nz);
         if (!fin) {
@@ -568,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             // bounce-back: bisection for the sdf's zero along the drift, every
             // probe on the position grid; the particle goes to the last probe
             // on the fluid side (the start, t = 0, if none) and its velocity is
-            // reversed (walls at rest)
+            // reversed in the frame of the wall: v -> 2 u_wall - v
             const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
             float lo = 0.0f, hi = 1.0f;
             for (int it = 0; it < kBounceIters; ++it) {
@@ -582,7 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
             ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
             nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
-            vx = -vx; vy = -vy; vz = -vz;
+            const float3 u = wall_velocity(nx, ny, nz, sc);           // reversal in the wall's frame
+            vx = fmaf(2.0f, u.x, -vx); vy = fmaf(2.0f, u.y, -vy); vz = fmaf(2.0f, u.z, -vz);
         }
         if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
         if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];

@@ -20,7 +20,7 @@ POS, VEL, VEL_CENTRED, FORCE = 0, 1, 2, 3
 FLAG_VIRIAL = 1
 FLAG_REFERENCE_FORCE = 2
 FLAG_BODY_UNIFORM = 4
-WALL_NONE, WALL_PLATES, WALL_PIPE = 0, 1, 2
+WALL_NONE, WALL_PLATES, WALL_PIPE, WALL_CYLINDERS = 0, 1, 2, 3
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE",
           EAGAIN: "EAGAIN", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND"}
@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("body_f", ctypes.c_double),
                 ("flow_axis", ctypes.c_int32), ("grad_axis", ctypes.c_int32),
                 ("profile_bins", ctypes.c_int32), ("flags", ctypes.c_int32), ("kexp", ctypes.c_double),
-                ("wall_kind", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("wall_h", ctypes.c_double)]
+                ("wall_kind", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("wall_h", ctypes.c_double),
+                ("wall_r_in", ctypes.c_double), ("omega_in", ctypes.c_double), ("omega_out", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -181,11 +182,15 @@ def batch_workspace_bytes(nboxes):
 
 
 def make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, mass=1.0, body_f=0.0, flow_axis=0, grad_axis=1,
-                profile_bins=0, flags=0, kexp=1.0, wall_kind=0, wall_h=0.0):
+                profile_bins=0, flags=0, kexp=1.0, wall_kind=0, wall_h=0.0, wall_r_in=0.0, omega_in=0.0,
+                omega_out=0.0):
     """kexp: exponent k of the random-term kernel w_R = (1 - r)^k (0 < k <= 1).
-    wall_kind: WALL_NONE, WALL_PLATES (half-gap wall_h) or WALL_PIPE (radius wall_h)."""
+    wall_kind: WALL_NONE, WALL_PLATES (half-gap wall_h), WALL_PIPE (radius
+    wall_h) or WALL_CYLINDERS (radii wall_r_in < wall_h, turning at omega_in
+    and omega_out about +flow_axis)."""
     return Params(float(a), float(gamma), float(kT), float(dt), float(mass), float(body_f), int(flow_axis),
-                  int(grad_axis), int(profile_bins), int(flags), float(kexp), int(wall_kind), 0, float(wall_h))
+                  int(grad_axis), int(profile_bins), int(flags), float(kexp), int(wall_kind), 0, float(wall_h),
+                  float(wall_r_in), float(omega_in), float(omega_out))
 
 
 def _as_arg(arr, dtype, shape_tail):

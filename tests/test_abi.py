@@ -50,9 +50,9 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(dpd_geom), sizeof(dpd_params), sizeof(dpd_stats), sizeof(dpd_request),
          sizeof(dpd_result));
-  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(dpd_params, flow_axis), offsetof(dpd_params, flags),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(dpd_params, flow_axis), offsetof(dpd_params, flags),
          offsetof(dpd_stats, nsamples), offsetof(dpd_stats, escaped), offsetof(dpd_params, kexp),
-         offsetof(dpd_params, wall_h));
+         offsetof(dpd_params, wall_h), offsetof(dpd_params, omega_out));
   return 0;
 }
 """)
@@ -64,7 +64,8 @@ int main(void) {
     assert sizes == [ctypes.sizeof(dpd.Geom), ctypes.sizeof(dpd.Params), ctypes.sizeof(dpd.Stats),
                      ctypes.sizeof(dpd.Request), ctypes.sizeof(dpd.Result)]
     assert offs == [dpd.Params.flow_axis.offset, dpd.Params.flags.offset, dpd.Stats.nsamples.offset,
-                    dpd.Stats.escaped.offset, dpd.Params.kexp.offset, dpd.Params.wall_h.offset]
+                    dpd.Stats.escaped.offset, dpd.Params.kexp.offset, dpd.Params.wall_h.offset,
+                    dpd.Params.omega_out.offset]
 
 
 @pytest.mark.parametrize("cells", [(3, 3, 3), (8, 8, 8), (48, 48, 48), (192, 96, 96), (7, 64, 5), (127, 3, 3)])

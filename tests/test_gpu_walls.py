@@ -182,3 +182,70 @@ def test_wall_errors():
     s = b.wall_sdf()
     np.testing.assert_allclose(s, np.abs(pos[:, 1].astype(np.float64) - 4.0) - 2.5, atol=1e-6)
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# turning coaxial cylinders (Taylor-Couette, Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def test_cylinders_one_step_matches_oracle():
+    cells, r_in, r_out, w_in, w_out = (6, 14, 14), 2.5, 5.5, -0.15, 0.2
+    geo = dpd.make_params(wall_kind=dpd.WALL_CYLINDERS, wall_h=r_out, wall_r_in=r_in, omega_in=w_in,
+                          omega_out=w_out, dt=0.01)
+    pos, vel, frozen = walls.carve(cells, 3.0, dpd.make_params(dt=0.01), dpd.WALL_CYLINDERS, r_out, seed=67,
+                                   equil_steps=200, wall_r_in=r_in)
+    base = oracle.make_params(a=geo.a, gamma=geo.gamma, kT=geo.kT, dt=geo.dt)
+    q = oracle.with_walls(base, 3, r_out, frozen.astype(np.uint8), r_in=r_in, omega_in=w_in, omega_out=w_out)
+    x = pos.astype(np.float64)
+    s = oracle.sdf(x, cells, q)
+    c = x.copy()
+    c[:, 0] = 0.0
+    c[:, 1:] -= np.asarray(cells[1:], dtype=np.float64) / 2
+    radial = c / np.linalg.norm(c, axis=1, keepdims=True)
+    near = (~frozen) & (s > -0.1)
+    outer = np.linalg.norm(c, axis=1) > 0.5 * (r_in + r_out)
+    vel = vel.copy()
+    vel[near] += (8.0 * np.where(outer[near, None], radial[near], -radial[near])).astype(np.float32)
+    vel[frozen] = oracle.wall_velocity(x[frozen], cells, q).astype(np.float32)
+    b = dpd.Box(cells, len(pos), params=geo, seed=67)
+    b.set_state(pos, vel)
+    b.set_frozen(frozen)
+    np.testing.assert_allclose(b.read(dpd.VEL)[frozen], vel[frozen], rtol=0, atol=1e-6)   # the walls' velocity
+    b.step(1)
+    fg, xg, vg = b.read(dpd.FORCE), b.read(dpd.POS).astype(np.float64), b.read(dpd.VEL).astype(np.float64)
+    b.close()
+    ids = np.arange(len(pos), dtype=np.uint32)
+    fo, so, _ = oracle.forces(pos, vel, ids, cells, q, 0, 67)
+    err = np.linalg.norm(fg.astype(np.float64) - fo, axis=1)
+    assert np.all(err <= TOL_F * so)
+    xo, vo = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    oracle.step(xo, vo, ids, cells, q, 67, 0, 1, want_diag=False)
+    vk = vel.astype(np.float64) + geo.dt * fo
+    bounced = (~frozen) & (np.abs(vo - vk).max(axis=1) > 1e-9)
+    _say(f"[cylinders] {bounced.sum()} fluid particles bounced")
+    assert bounced.sum() >= 10
+    tol_v = 0.01 * TOL_F * so[:, None] + 4 * np.spacing(np.abs(vo).astype(np.float32)).astype(np.float64) + 1e-6
+    assert np.all(np.abs(vg - vo) <= tol_v)
+    qg = dpd.position_grid(cells)
+    dx = np.abs(xg - xo)
+    assert np.all(dx <= 2 * qg + 0.01 * np.abs(vg - vo) + 1e-6)     # frozen layers turned, fluid bounced
+
+
+def test_taylor_couette_profile_on_gpu():
+    """The outer cylinder turning, the inner at rest: A r + B / r."""
+    r = walls.taylor_couette(r_in=4.0, r_out=10.0, omega_in=0.0, omega_out=0.05, rho=3.0, a=25.0, gamma=4.5,
+                             kT=1.0, k=1.0, dt=0.01, length=8, eta_guess=0.95, warm_tau=6.0, avg_tau=6.0,
+                             samples=150, nbins=12)
+    dev = np.abs(r["v"] - r["v_analytic"])[1:-1]
+    _say(f"[taylor-couette] v {np.round(r['v'], 3)} analytic {np.round(r['v_analytic'], 3)}")
+    assert dev.max() < 0.05 * 0.05 * 10.0, dev.max()
+
+
+def test_cylinder_errors():
+    b = dpd.Box((6, 14, 14), 1000, params=dpd.make_params(), seed=68)
+    for kw in (dict(wall_h=5.0, wall_r_in=5.0), dict(wall_h=5.0, wall_r_in=0.0), dict(wall_h=6.5, wall_r_in=2.0),
+               dict(wall_h=5.0, wall_r_in=2.0, omega_out=float("inf"))):
+        with pytest.raises(dpd.DPDError) as e:
+            b.set_params(dpd.make_params(wall_kind=dpd.WALL_CYLINDERS, **kw))
+        assert e.value.code == dpd.EINVAL
+    b.close()
