@@ -209,6 +209,56 @@ def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
     return out
 
 
+BIN_BYTES = 89.0        # per particle: key read, counts, scan, scatter and gather of pos, vel
+INTEGRATE_BYTES = 80.0  # per particle: pos, vel, force read; pos, vel written
+
+
+def stage_roofline(n, stage):
+    """Algorithmic HBM GB/s and fraction of the 8 TB/s peak of the binning
+    and integrate stages (HBM-bound by their byte counts)."""
+    out = {}
+    for name, per in (("bin", BIN_BYTES), ("integrate", INTEGRATE_BYTES)):
+        gbps = n * per / (stage[name] / 1e3) / 1e9
+        out[name] = {"bytes_per_particle": per, "GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+    return out
+
+
+def bench_large(steps=50, warmup=5):
+    """One GPU's share of a large periodic-Poiseuille run: 192 x 96 x 96
+    cells at rho = 8 (14.2 M particles), drive 0.05 along x, 96-slab FP64
+    flow profile.  Throughput, per-stage time and the stages' rooflines."""
+    import torch
+    from paper_1911_04712_amd import dpd, inputs
+    w = inputs.WORKLOADS["pp192x96x96_rho8"]
+    n = w.n
+    rho = n / float(w.cells[0] * w.cells[1] * w.cells[2])
+    pos, vel = inputs.uniform_state(w.cells, n=n, kT=w.kT, seed=w.seed)
+    p = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass, body_f=w.body_f,
+                        profile_bins=w.profile_bins)
+    box = dpd.Box(w.cells, n, params=p, seed=w.seed)
+    box.set_state(pos, vel)
+    del pos, vel
+    tile = list(box.tune_tile(reps=2)[0])
+    box.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    box.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    stage = box.profile_steps(10)
+    st = box.stats()
+    out = {"workload": f"{w.name}: {list(w.cells)} cells, rho = 8, drive {w.body_f}, {w.profile_bins}-slab profile",
+           "particles": n, "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "steps": steps,
+           "tile": tile, "force_threads": box.get_force_threads(), "ms_per_step": ms / steps,
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "force_frac_of_alu_peak": round(force_ops(n, rho) / (stage["force"] / 1e3) / 1e12 / VALU_PEAK_TOPS, 4),
+           "stages_hbm": stage_roofline(n, stage), "kT_centred_last": st["kT_centred"], "nonfinite": st["nonfinite"]}
+    box.close()
+    return out
+
+
 def bench_walls(steps=500, warmup=30, R=20.0, length=48):
     """Pipe flow: the rho = 3 fluid of the main workload in a pipe of radius
     20 along x (frozen wall layer cut from the equilibrated fluid, uniform
@@ -329,6 +379,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-species", action="store_true", help="skip the two-species measurement")
     ap.add_argument("--no-walls", action="store_true", help="skip the pipe-flow (walls) measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the 14.2 M-particle rho = 8 measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device copy of this many MiB (reference for HBM counters)")
@@ -397,6 +448,7 @@ def main():
                       "gamma": w.gamma, "kT": w.kT, "dt": w.dt, "body_f": w.body_f, "reductions": "f64",
                       "parallelism": "single GPU"},
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "stages_hbm": stage_roofline(n, stage),
            "wall_s": round(wall, 3),
            "roofline": roofline}
 
@@ -437,6 +489,8 @@ def main():
         out["species"] = bench_species(w, check=not args.no_cpu_baseline)
     if not args.no_walls:
         out["walls"] = bench_walls()
+    if not args.no_large:
+        out["large"] = bench_large()
     if not args.no_batched:
         out["batched"] = bench_batched()
     if not args.no_served:
