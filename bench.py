@@ -69,6 +69,21 @@ def measured_traffic(workload):
     return int(rec["traffic_bytes_per_launch"])
 
 
+def run_env():
+    """What the numbers were measured on: GPU, ROCm/HIP and torch versions,
+    host threads, and the source revision when a git checkout is present."""
+    import subprocess
+    import torch
+    rev = None
+    try:
+        rev = subprocess.run(["git", "rev-parse", "--short", "HEAD"], cwd=ROOT, capture_output=True, text=True,
+                             timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"gpu": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__,
+            "nproc": os.cpu_count(), "git": rev}
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -450,7 +465,8 @@ def main():
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
            "stages_hbm": stage_roofline(n, stage),
            "wall_s": round(wall, 3),
-           "roofline": roofline}
+           "roofline": roofline,
+           "env": run_env()}
 
     if not args.no_cpu_baseline:
         import oracle

@@ -274,6 +274,13 @@ int dpd_set_seed(dpd_box box, uint64_t seed);
  * the accumulators.  Synchronises the stream. */
 int dpd_set_state(dpd_box box, const float* pos_n3, const float* vel_n3, int where);
 
+/* Set the step counter: the index of the next force evaluation, which
+ * selects the random term's noise.  With dpd_set_state of a run's DPD_POS and
+ * DPD_VEL (and dpd_set_types / dpd_set_frozen), this resumes the run: the
+ * trajectory continues bit for bit, whatever the internal order (forces are
+ * order-independent sums).  DPD_ESTATE without a state.  Synchronises. */
+int dpd_set_step(dpd_box box, uint64_t step);
+
 /* Load a random state generated on the device: positions uniform on [0, L)
  * (on the position grid), velocities Maxwellian N(0, kT/m) per component
  * with the centre-of-mass velocity removed, particle i = id i.  Drawn from

@@ -664,6 +664,16 @@ int dpd_set_seed(dpd_box b, uint64_t seed)
     return push_desc(b);
 }
 
+int dpd_set_step(dpd_box b, uint64_t step)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_set_step: null box");
+    if (!b->have_state) return fail(DPD_ESTATE, "dpd_set_step: no state loaded");
+    HIPCHK(hipStreamSynchronize(b->stream));           // no step may be in flight
+    const unsigned long long s = step;
+    HIPCHK(hipMemcpyAsync(&b->hd.st->step, &s, sizeof s, hipMemcpyHostToDevice, b->stream));
+    return sync_box(b);
+}
+
 int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where)
 {
     if (!b) return fail(DPD_EINVAL, "dpd_set_state: null box");

@@ -558,9 +558,11 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
         float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
               nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
+        bool turned = false;
         if (kWalls && frozen && sc.wall_kind == 3) {
             // a turning cylinder turns its frozen layer rigidly by omega dt
-            // about the axis; the particle carries the wall velocity there
+            // about the axis (the particle takes the wall velocity at its
+            // new, grid-rounded position below)
             float c1, c2;
             const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
             if (sc.omega[cyl] != 0.0f) {
@@ -569,8 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
                 nx = x.x + d.x;
                 ny = x.y + d.y;
                 nz = x.z + d.z;
-                const float3 u = wall_velocity(nx, ny, nz, sc);
-                vx = u.x; vy = u.y; vz = u.z;
+                turned = true;
             }
         }
         const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) &&
@@ -583,6 +584,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         nx = rintf(nx * sc.inv_q) * sc.q;
         ny = rintf(ny * sc.inv_q) * sc.q;
         nz = rintf(nz * sc.inv_q) * sc.q;
+        if (turned) {                   // the same velocity dpd_set_frozen gives a particle there
+            const float3 u = wall_velocity(nx, ny, nz, sc);
+            vx = u.x; vy = u.y; vz = u.z;
+        }
         if (kWalls && sc.wall_kind != 0 && live && !frozen && fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
             // bounce-back: bisection for the sdf's zero along the drift, every
             // probe on the position grid; the particle goes to the last probe

@@ -103,6 +103,7 @@ SIGNATURES = {
     "dpd_server_clock": ([_VP], ctypes.c_double),
     "dpd_server_destroy": ([_VP], ctypes.c_int),
     "dpd_set_state": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
+    "dpd_set_step": ([_VP, ctypes.c_uint64], ctypes.c_int),
     "dpd_set_species": ([_VP, ctypes.c_int32, _VP, _VP, _VP], ctypes.c_int),
     "dpd_get_species": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "dpd_set_types": ([_VP, _VP], ctypes.c_int),
@@ -270,6 +271,10 @@ class Box:
         if wp != wv:
             raise ValueError("pos and vel must both be host arrays or both device tensors")
         _check(lib().dpd_set_state(self._h, pp, vp, wp))
+
+    def set_step(self, step):
+        """Index of the next force evaluation (resuming a run)."""
+        _check(lib().dpd_set_step(self._h, int(step)))
 
     def set_species(self, a_tab=None, gamma_tab=None, rc_tab=None):
         """Per species-pair a, gamma and cutoff (symmetric ntypes x ntypes
