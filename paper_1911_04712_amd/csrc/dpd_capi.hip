@@ -97,7 +97,7 @@ Layout make_layout(int64_t n, int64_t nc)
     L.out = take(nn * 3 * sizeof(float));
     L.count = take((size_t)nc * sizeof(int));
     L.cell_start = take((size_t)(nc + 1) * sizeof(int));
-    L.bsum = take((size_t)((nc + kScanChunk - 1) / kScanChunk) * sizeof(int));
+    L.bsum = take((size_t)((nc + kSubChunk - 1) / kSubChunk) * sizeof(int));
     L.partials = take((size_t)kIntegrateMaxBlocks * kPartials * sizeof(double));
     L.profile = take((size_t)kProfileMaxBins * 2 * sizeof(long long));
     L.stats = take(sizeof(DevStats));
@@ -298,6 +298,7 @@ int push_desc(dpd_box_s* b)
     d.n = b->n;
     d.nc = b->nc;
     d.nchunks = (b->nc + dpd::kScanChunk - 1) / dpd::kScanChunk;
+    d.nsub = (b->nc + dpd::kSubChunk - 1) / dpd::kSubChunk;
     d.nblk_int = dpd::integrate_blocks(b->n);
     d.flags = b->have_params ? b->params.flags : 0;
     if (b->have_params) {
@@ -435,6 +436,7 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
     hipError_t e = hipSuccess;
     if (rc == DPD_OK) {
         e = dpd::launch_fill_i32(b->hd.count, 0, nc, b->stream);
+        if (e == hipSuccess) e = dpd::launch_fill_i32(b->hd.bsum, 0, b->hd.nsub, b->stream);
         if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->hd.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
         if (e == hipSuccess)
             e = dpd::launch_fill_i32((int*)b->hd.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
@@ -693,11 +695,12 @@ int dpd_set_state(dpd_box b, const float* pos_n3, const float* vel_n3, int where
     }
     HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
     HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
+    HIPCHK(dpd::launch_fill_i32(d.bsum, 0, d.nsub, b->stream));
     HIPCHK(dpd::launch_fill_i32((int*)d.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream));
     HIPCHK(dpd::launch_fill_i32((int*)d.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream));
     HIPCHK(dpd::launch_load_state(pp, vp, b->n, d.pos_a, d.vel_a, (float)b->q, (float)(1.0 / b->q), b->L, b->flags,
                                   b->stream));
-    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
+    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.bsum, d.keyslot, b->stream));
     HIPCHK(dpd::launch_count_nonempty(d.count, b->nc, b->flags + 1, b->stream));
     int bad[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(bad, b->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream));
@@ -722,13 +725,14 @@ int dpd_init_random(dpd_box b, double kT, uint64_t seed)
     const dpd::BoxDesc& d = b->hd;
     HIPCHK(dpd::launch_fill_i32(b->flags, 0, 4, b->stream));
     HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
+    HIPCHK(dpd::launch_fill_i32(d.bsum, 0, d.nsub, b->stream));
     HIPCHK(dpd::launch_fill_i32((int*)d.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream));
     HIPCHK(dpd::launch_fill_i32((int*)d.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream));
     // the id-order staging buffer (12 B per particle) holds the per-block sums
     const int scratch = (int)std::min<int64_t>((int64_t)b->n * 3 / 2, (int64_t)1 << 30);
     HIPCHK(dpd::launch_init_random(b->n, b->L, (float)b->q, std::sqrt(kT / b->params.mass), seed, d.pos_a, d.vel_a,
                                    (double*)b->out, scratch, b->stream));
-    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.keyslot, b->stream));
+    HIPCHK(dpd::launch_keys(d.pos_a, b->n, b->cells, d.count, d.bsum, d.keyslot, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     b->rho_occ = 0.0;                   // uniform positions
     const int rc = push_desc(b);        // no frozen particles

@@ -12,6 +12,8 @@ constexpr int kBlock = 256;             // threads per block of the streaming ke
 constexpr int kForceBlock = 512;        // default threads per workgroup of the tiled pair-force kernel
 constexpr int kForceBlocks[3] = {256, 512, 1024};   // the instantiated workgroup sizes
 constexpr int kScanChunk = 512;         // cells per block of the cell-count scan (2 per thread)
+constexpr int kSubChunk = 64;             // cells per device counter of the chunk sums
+static_assert(kScanChunk % kSubChunk == 0, "chunks are whole sub-chunks");
 constexpr int kIntegrateMaxBlocks = 2048;
 constexpr int kProfileMaxBins = 4096;
 constexpr int kPartials = 5;            // P_x, P_y, P_z, KE_half, KE_centred
@@ -153,11 +155,11 @@ struct BoxDesc {
     int* perm;                 // cell order -> index into pos_a (arrival order)
     int* count;                // particles per cell (zeroed by the scan)
     int* cell_start;           // nc + 1
-    int* bsum;                 // chunk sums of count
+    int* bsum;                 // particles per kSubChunk cells (zeroed by the scatter)
     double* partials;          // integrate per-block partials (kPartials each)
     long long* profile;        // flow profile accumulators (sum, count) per slab
     DevStats* st;
-    int n, nc, nchunks;
+    int n, nc, nchunks, nsub;
     int nblk_int;              // integrate blocks of this box (depends on n only)
     int flags;                 // DPD_FLAG_* of the box
     int pad0;
@@ -195,7 +197,7 @@ struct Layout {
     size_t out;               // float[3n]  staging of reads and writes in id order
     size_t count;             // int[nc]    particles per cell
     size_t cell_start;        // int[nc+1]
-    size_t bsum;              // int[nchunks]
+    size_t bsum;              // int[nsub]
     size_t partials;          // double[kIntegrateMaxBlocks * kPartials]
     size_t profile;           // long long[kProfileMaxBins * 2] (sum, count)
     size_t stats;             // DevStats
@@ -216,7 +218,8 @@ hipError_t launch_load_state(const float* pos3, const float* vel3, int n, float4
                              float q, float inv_q, const float* L, int* bad, hipStream_t s);
 hipError_t launch_init_random(int n, const float* L, float q, double vscale, uint64_t seed, float4* pos, float4* vel,
                               double* scratch, int scratch_doubles, hipStream_t s);
-hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s);
+hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int* bsum, int2* keyslot,
+                       hipStream_t s);
 // species by id -> vel[i].w of the particle whose id is pos[i].w, and back
 hipError_t launch_set_types(const float4* pos, float4* vel, int n, const int* type_by_id, hipStream_t s);
 hipError_t launch_get_types(const float4* pos, const float4* vel, int n, int* type_by_id, hipStream_t s);

@@ -4,12 +4,13 @@
 // Binning (Sec. 3.2 of the Mirheo paper: cells of edge r_c, particles sorted
 // by cell) is a counting sort made stable and deterministic:
 //   keys    -- cell of each particle and an arrival slot from an atomic
-//              per-cell counter (fused into the integrate kernel, or k_keys
-//              after a state load);
-//   chunk   -- sums of 2048-cell chunks;
+//              per-cell counter, plus particle counts per kSubChunk cells
+//              from a second counter (fused into the integrate kernel, or
+//              k_keys after a state load);
 //   scan    -- each block scans its chunk after a block-wide reduction of the
 //              chunk sums before it, giving cell_start; counters are zeroed;
 //   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary);
+//              the sub-chunk counts are zeroed for the next step;
 //   gather  -- each particle's final place is cell_start + its rank by
 //              previous index among the cell's members, so the order inside a
 //              cell is the previous array order whatever the atomics did.
@@ -49,6 +50,26 @@ __device__ __forceinline__ ArrivalTicket arrival_issue(int key, bool valid, int*
     t.base = 0;
     if (head) t.base = atomicAdd(&count[key], run_end - lane);
     return t;
+}
+
+// Particle counts per sub-chunk of kSubChunk cells, one device atomic per
+// run of equal sub-chunks in a wave.  Same-address device atomics
+// serialise, so the counters are kept small enough that only a few waves
+// (about kSubChunk rho / 64) add to each.  Same contract as arrival_issue;
+// nothing is returned.
+__device__ __forceinline__ void chunk_add(int key, bool valid, int* __restrict__ bsum)
+{
+    const int lane = threadIdx.x & 63;
+    const int ck = valid ? key / kSubChunk : -1;
+    const int prev = __shfl_up(ck, 1, 64);
+    const bool head = valid && (lane == 0 || prev != ck);
+    const unsigned long long heads = __ballot(head);
+    const int nlive = __popcll(__ballot(valid));                    // valid lanes are a prefix
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const unsigned long long after = heads & ~upto;
+    int run_end = after ? __ffsll((long long)after) - 1 : 64;
+    if (run_end > nlive) run_end = nlive;
+    if (head) atomicAdd(&bsum[ck], run_end - lane);
 }
 
 // Second half: every lane of the wave must call it.
@@ -189,21 +210,24 @@ hipError_t launch_init_random(int n, const float* L, float q, double vscale, uin
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
+// count and bsum must be zero on entry.
 __global__ void k_keys(const float4* __restrict__ pos, int n, int Lx, int Ly, int Lz, int* __restrict__ count,
-                       int2* __restrict__ keyslot)
+                       int* __restrict__ bsum, int2* __restrict__ keyslot)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 p = pos[i];
     const int c = cell_of(p.x, p.y, p.z, Lx, Ly, Lz);
     keyslot[i] = make_int2(c, atomicAdd(&count[c], 1));
+    atomicAdd(&bsum[c / kSubChunk], 1);
 }
 
-hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int2* keyslot, hipStream_t s)
+hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int* bsum, int2* keyslot,
+                       hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_keys, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, n, cells[0], cells[1],
-                       cells[2], count, keyslot);
+                       cells[2], count, bsum, keyslot);
     return hipGetLastError();
 }
 
@@ -335,27 +359,13 @@ int box_work(const BoxDesc& d, int kind)
 {
     switch (kind) {
     case kWChunk: return d.nchunks + 1;                      // + one block that folds the reductions
-    case kWPart: return (d.n + kBlock - 1) / kBlock;
+    case kWPart: {                                           // also covers the chunk sums k_scatter zeroes
+        const int np = (d.n + kBlock - 1) / kBlock, nk = (d.nsub + kBlock - 1) / kBlock;
+        return np > nk ? np : nk;
+    }
     case kWTile: return ((d.tc.ntiles + 7) / 8) * 8;       // padded for the XCD swizzle
     default: return d.nblk_int;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
-                                                       int nbox)
-{
-    DPD_BOX_OF(kWChunk)
-    if (lb >= d.nchunks) return;
-    __shared__ int scratch[kBlock / 64];
-    const int base = lb * kScanChunk;
-    int v = 0;
-#pragma unroll
-    for (int k = 0; k < kScanChunk / kBlock; ++k) {
-        const int c = base + k * kBlock + threadIdx.x;
-        if (c < d.nc) v += d.count[c];
-    }
-    v = block_sum(v, scratch);
-    if (threadIdx.x == 0) d.bsum[lb] = v;
 }
 
 __device__ void fold_stats(const BoxDesc& d);
@@ -372,9 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
     }
     const int nc = d.nc;
     int* __restrict__ count = d.count;
-    // prefix of this chunk: sum of the chunk sums before it
+    // prefix of this chunk: sum of the sub-chunk counts before it
     int prefix = 0;
-    for (int k = threadIdx.x; k < lb; k += kBlock) prefix += d.bsum[k];
+    const int nk = lb * (kScanChunk / kSubChunk);
+    for (int k = threadIdx.x; k < nk; k += kBlock) prefix += d.bsum[k];
     prefix = block_sum(prefix, scratch);
 
     const int c0 = lb * kScanChunk + threadIdx.x * per;
@@ -408,6 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BoxDesc* __restrict__ 
 {
     DPD_BOX_OF(kWPart)
     const int i = lb * kBlock + threadIdx.x;
+    if (i < d.nsub) d.bsum[i] = 0;               // the scan has read them; the next keys add to zero
     if (i >= d.n) return;
     const int2 ks = d.keyslot[i];
     d.perm[d.cell_start[ks.x] + ks.y] = i;
@@ -431,10 +443,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
 
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s)
 {
-    if (lp.total[kWChunk] > 0) {
-        hipLaunchKernelGGL(k_chunk_sums, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    if (lp.total[kWChunk] > 0)
         hipLaunchKernelGGL(k_scan, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
-    }
     if (lp.total[kWPart] > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
         hipLaunchKernelGGL(k_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
@@ -620,6 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         }
         const int c = live ? cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
         const ArrivalTicket tk = arrival_issue(c, live, d.count);     // atomic in flight meanwhile
+        chunk_add(c, live, d.bsum);
         if (live) {
             pos_a[i] = make_float4(nx, ny, nz, x.w);
             vel_a[i] = make_float4(vx, vy, vz, v.w);              // .w: species
