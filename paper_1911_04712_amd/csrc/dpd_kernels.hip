@@ -5,8 +5,8 @@
 // by cell) is a counting sort made stable and deterministic:
 //   keys    -- cell of each particle and an arrival slot from an atomic
 //              per-cell counter, plus particle counts per kSubChunk cells
-//              from a second counter (fused into the integrate kernel, or
-//              k_keys after a state load);
+//              from a second counter (fused into the integrate kernel; after
+//              a state load, k_keys and k_sub_sums);
 //   scan    -- each block scans its chunk after a block-wide reduction of the
 //              chunk sums before it, giving cell_start; counters are zeroed;
 //   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary);
@@ -210,16 +210,33 @@ hipError_t launch_init_random(int n, const float* L, float q, double vscale, uin
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
-// count and bsum must be zero on entry.
+// count must be zero on entry.
 __global__ void k_keys(const float4* __restrict__ pos, int n, int Lx, int Ly, int Lz, int* __restrict__ count,
-                       int* __restrict__ bsum, int2* __restrict__ keyslot)
+                       int2* __restrict__ keyslot)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float4 p = pos[i];
-    const int c = cell_of(p.x, p.y, p.z, Lx, Ly, Lz);
-    keyslot[i] = make_int2(c, atomicAdd(&count[c], 1));
-    atomicAdd(&bsum[c / kSubChunk], 1);
+    const bool live = i < n;                      // a prefix of each wave; every lane takes part below
+    int c = -1;
+    if (live) {
+        const float4 p = pos[i];
+        c = cell_of(p.x, p.y, p.z, Lx, Ly, Lz);
+    }
+    const ArrivalTicket tk = arrival_issue(c, live, count);
+    const int slot = arrival_finish(tk, live);
+    if (live) keyslot[i] = make_int2(c, slot);
+}
+
+// Sub-chunk counts from the cell counts, one wave per sub-chunk.  A state
+// load is in no particular cell order, so counting through chunk_add would
+// put every particle's atomic on a few hundred addresses.
+__global__ __launch_bounds__(kBlock) void k_sub_sums(const int* __restrict__ count, int nc, int nsub,
+                                                     int* __restrict__ bsum)
+{
+    static_assert(kSubChunk == 64, "one lane per cell of a sub-chunk");
+    const int k = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int c = k * kSubChunk + (int)(threadIdx.x & 63);
+    const int t = wave_sum(c < nc ? count[c] : 0);   // uniform per wave: every lane takes part
+    if (k < nsub && (threadIdx.x & 63) == 0) bsum[k] = t;
 }
 
 hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, int* bsum, int2* keyslot,
@@ -227,7 +244,11 @@ hipError_t launch_keys(const float4* pos, int n, const int* cells, int* count, i
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_keys, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, n, cells[0], cells[1],
-                       cells[2], count, bsum, keyslot);
+                       cells[2], count, keyslot);
+    const int nc = cells[0] * cells[1] * cells[2];
+    const int nsub = (nc + kSubChunk - 1) / kSubChunk;
+    const int per = kBlock / 64;
+    hipLaunchKernelGGL(k_sub_sums, dim3((nsub + per - 1) / per), dim3(kBlock), 0, s, count, nc, nsub, bsum);
     return hipGetLastError();
 }
 
@@ -383,9 +404,22 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
     const int nc = d.nc;
     int* __restrict__ count = d.count;
     // prefix of this chunk: sum of the sub-chunk counts before it
-    int prefix = 0;
-    const int nk = lb * (kScanChunk / kSubChunk);
-    for (int k = threadIdx.x; k < nk; k += kBlock) prefix += d.bsum[k];
+    // (a whole number of int4s: chunks are 8 sub-chunks, the array 256-byte aligned)
+    static_assert((kScanChunk / kSubChunk) % 4 == 0, "int4 reads of whole chunks");
+    const int4* __restrict__ b4 = reinterpret_cast<const int4*>(d.bsum);
+    const int nk4 = lb * (kScanChunk / kSubChunk / 4);
+    int p0 = 0, p1 = 0;
+    int k = threadIdx.x;
+    for (; k + kBlock < nk4; k += 2 * kBlock) {
+        const int4 u = b4[k], v = b4[k + kBlock];
+        p0 += (u.x + u.y) + (u.z + u.w);
+        p1 += (v.x + v.y) + (v.z + v.w);
+    }
+    if (k < nk4) {
+        const int4 u = b4[k];
+        p0 += (u.x + u.y) + (u.z + u.w);
+    }
+    int prefix = p0 + p1;
     prefix = block_sum(prefix, scratch);
 
     const int c0 = lb * kScanChunk + threadIdx.x * per;

@@ -394,8 +394,29 @@ def test_empty_and_single_particle_boxes():
     b.set_state(pos, vel)
     b.step(3)
     f = b.read(dpd.FORCE)
-    np.testing.assert_array_equal(f, [[-0.2, 0.0, 0.0]] if False else [[np.float32(-0.2), 0.0, 0.0]])
+    np.testing.assert_array_equal(f, [[np.float32(-0.2), 0.0, 0.0]])
     b.close()
+
+
+def test_periodic_pair_worked_example():
+    # the two-particle example across the periodic face of an 8^3 box
+    # (Eqs. 3-5 worked by hand; the same numbers pin the oracle), through
+    # the C-ABI: the force after one step is the step-0 force
+    pos = np.array([[0.125, 4.0, 4.0], [7.75, 4.25, 3.875]], np.float32)
+    vel = np.array([[0.5, -0.25, 0.125], [-0.25, 0.5, 0.0]], np.float32)
+    fc = np.array([10.669593143432, -7.113062095621, 3.556531047811])
+    fd = np.array([-1.058714025971, 0.705809350647, -0.352904675324])
+    fr1 = np.array([12.803511772118, -8.535674514745, 4.267837257373])
+    for kT, seed in ((0.0, 3), (1.0, 11)):
+        b = _box((8, 8, 8), pos, vel, dpd.make_params(a=25.0, gamma=4.5, kT=kT, dt=0.01), seed)
+        b.step(1)
+        f = b.read(dpd.FORCE).astype(np.float64)
+        b.close()
+        expect = fc + fd + (oracle.xi(0, 1, 0, seed) * fr1 if kT else 0.0)
+        s = np.abs(fc).sum() + np.abs(fd).sum() + (np.abs(fr1).sum() * 4.0 if kT else 0.0)
+        _say(f"[example B] kT={kT}: gpu {f[0]}, expect {expect}")
+        assert np.all(np.abs(f[0] - expect) <= TOL_F * s), (f[0], expect)
+        np.testing.assert_array_equal(f[1], -f[0])          # the pair halves are exact negatives
 
 
 # ---------------------------------------------------------------------------

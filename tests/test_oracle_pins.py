@@ -97,6 +97,30 @@ def test_newton_third_law_and_periodic_image():
         np.testing.assert_allclose(F_img, F_ij, rtol=1e-12, atol=1e-12)
 
 
+# A pair across the periodic face of an 8^3 box whose coordinates are exact
+# in binary: i = (0.125, 4, 4), j = (7.75, 4.25, 3.875), minimum image
+# r_ij = (0.375, -0.25, 0.125), v_ij = (0.75, -0.75, 0.125).  The numbers are
+# worked by hand from Eqs. 3-5 (k = 1, r_c = 1): r = sqrt(0.21875),
+# w = 1 - r, e.v_ij = 0.484375 / r.
+EXB_RI, EXB_RJ = np.array([0.125, 4.0, 4.0]), np.array([7.75, 4.25, 3.875])
+EXB_VI, EXB_VJ = np.array([0.5, -0.25, 0.125]), np.array([-0.25, 0.5, 0.0])
+EXB_FC = np.array([10.669593143432, -7.113062095621, 3.556531047811])      # a = 25
+EXB_FD = np.array([-1.058714025971, 0.705809350647, -0.352904675324])      # gamma = 4.5
+EXB_FR1 = np.array([12.803511772118, -8.535674514745, 4.267837257373])     # sigma = 3, dt = 0.01, xi = 1
+
+
+def test_periodic_pair_worked_example():
+    hit, F, Fc, _ = oracle.pair_force(EXB_RI, EXB_RJ, EXB_VI, EXB_VJ, BOX8,
+                                      oracle.make_params(a=25.0, gamma=4.5, kT=0.0), 0, 1, 0, 5)
+    assert hit
+    np.testing.assert_allclose(Fc, EXB_FC, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(F, EXB_FC + EXB_FD, rtol=0, atol=1e-11)
+    # kT = 1 gives sigma^2 = 2 gamma kT = 9
+    hit, F, _, _ = oracle.pair_force(EXB_RI, EXB_RJ, EXB_VI, EXB_VJ, BOX8,
+                                     oracle.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01), 0, 1, 7, 5)
+    np.testing.assert_allclose(F, EXB_FC + EXB_FD + oracle.xi(0, 1, 7, 5) * EXB_FR1, rtol=0, atol=1e-10)
+
+
 def test_cutoff_and_coincident_pair():
     p = oracle.make_params(a=25.0, gamma=4.5, kT=1.0)
     ri = np.array([2.0, 2.0, 2.0])
