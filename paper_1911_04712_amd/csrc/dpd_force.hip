@@ -442,7 +442,11 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
         const int M = __builtin_amdgcn_readlane(rincl, 15);
         const int delta = rs - rpre;                // staged index = list position + delta
         for (int u0 = 0; u0 < M; u0 += 64) {
-            const int u = u0 + lane;
+            // a last stretch of at most 32 entries is tested by lane groups
+            // of 8, 16 or 32 lanes, one home particle per group
+            const int rem = M - u0;
+            const int gbits = rem <= 8 ? 3 : (rem <= 16 ? 4 : (rem <= 32 ? 5 : 6));   // wave-uniform
+            const int u = u0 + (lane & ((1 << gbits) - 1));
             int k = 0;
 #pragma unroll
             for (int st = 8; st > 0; st >>= 1)
@@ -470,6 +474,23 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
                     qt -= fh;
                 }
             };
+            if (gbits < 6) {
+                const int g = lane >> gbits, G = 64 >> gbits;
+                for (int a = own_s; a < own_e; a += G) {
+                    const int ah = a + g;
+                    const bool hv = ah < own_e;
+                    const float4 xa = sp[hv ? ah : a];
+                    const float r2 = dist2(xa.x - bx, xa.y - xb.y, xa.z - xb.z);
+                    const unsigned long long m = __builtin_amdgcn_ballot_w64(r2 < 1.0f) &
+                                                 __builtin_amdgcn_ballot_w64(hv && ub > (unsigned)(ah - own_s));
+                    const unsigned sl = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, (unsigned)qt));
+                    q[__builtin_amdgcn_inverse_ballot_w64(m) ? sl : qdummy] = ((unsigned)ah << 16) | (unsigned)b;
+                    qt += __popcll(m);
+                    drain();
+                }
+                continue;
+            }
             // home particles two at a time (the pair loop carries no odd-tail
             // logic), then the odd one
             int a = own_s;
