@@ -403,25 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
     }
     const int nc = d.nc;
     int* __restrict__ count = d.count;
-    // prefix of this chunk: sum of the sub-chunk counts before it
-    // (a whole number of int4s: chunks are 8 sub-chunks, the array 256-byte aligned)
-    static_assert((kScanChunk / kSubChunk) % 4 == 0, "int4 reads of whole chunks");
-    const int4* __restrict__ b4 = reinterpret_cast<const int4*>(d.bsum);
-    const int nk4 = lb * (kScanChunk / kSubChunk / 4);
-    int p0 = 0, p1 = 0;
-    int k = threadIdx.x;
-    for (; k + kBlock < nk4; k += 2 * kBlock) {
-        const int4 u = b4[k], v = b4[k + kBlock];
-        p0 += (u.x + u.y) + (u.z + u.w);
-        p1 += (v.x + v.y) + (v.z + v.w);
-    }
-    if (k < nk4) {
-        const int4 u = b4[k];
-        p0 += (u.x + u.y) + (u.z + u.w);
-    }
-    int prefix = p0 + p1;
-    prefix = block_sum(prefix, scratch);
-
+    // this chunk's counts first: their loads overlap the prefix below
     const int c0 = lb * kScanChunk + threadIdx.x * per;
     int v[per];
     int tsum = 0;
@@ -430,6 +412,25 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
         v[k] = (c0 + k < nc) ? count[c0 + k] : 0;
         tsum += v[k];
     }
+    // prefix of this chunk: sum of the sub-chunk counts before it
+    // (a whole number of int4s: chunks are 8 sub-chunks, the array 256-byte aligned)
+    static_assert((kScanChunk / kSubChunk) % 4 == 0, "int4 reads of whole chunks");
+    const int4* __restrict__ b4 = reinterpret_cast<const int4*>(d.bsum);
+    const int nk4 = lb * (kScanChunk / kSubChunk / 4);
+    int p0 = 0, p1 = 0;
+    int j = threadIdx.x;
+    for (; j + kBlock < nk4; j += 2 * kBlock) {
+        const int4 q0 = b4[j], q1 = b4[j + kBlock];
+        p0 += (q0.x + q0.y) + (q0.z + q0.w);
+        p1 += (q1.x + q1.y) + (q1.z + q1.w);
+    }
+    if (j < nk4) {
+        const int4 q0 = b4[j];
+        p0 += (q0.x + q0.y) + (q0.z + q0.w);
+    }
+    int prefix = p0 + p1;
+    prefix = block_sum(prefix, scratch);
+
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int incl = wave_incl_scan(tsum);
     if (lane == 63) wtot[wave] = incl;
@@ -467,12 +468,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
     if (p >= d.n) return;
     const int* __restrict__ perm = d.perm;
     const int i = perm[p];
+    const float4 x = d.pos_a[i], v = d.vel_a[i];     // in flight during the rank search
     const int c = d.keyslot[i].x;
     const int s = d.cell_start[c], e = d.cell_start[c + 1];
     int rank = 0;
     for (int t = s; t < e; ++t) rank += perm[t] < i;
-    d.pos_b[s + rank] = d.pos_a[i];
-    d.vel_b[s + rank] = d.vel_a[i];
+    d.pos_b[s + rank] = x;
+    d.vel_b[s + rank] = v;
 }
 
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s)
