@@ -1,7 +1,7 @@
 """The request server's pool allocator (host C++, csrc/pool_alloc.hpp),
 driven on the CPU: admission by HBM footprint carves each request's
 workspace out of one device pool first-fit, 256-byte aligned, and merges
-freed neighbours.  A driver built with g++ replays random admit/retire
+freed neighbours.  A small program built with g++ replays random admit/retire
 sequences; a plain Python first-fit model of the same policy must give the
 same offsets, no two live blocks may overlap, and retiring everything must
 leave one free block of the whole pool."""
@@ -14,7 +14,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_1911_04712_amd", "csrc")
 
-DRIVER = r"""
+REPLAY_SRC = r"""
 #include <cstdio>
 #include "pool_alloc.hpp"
 int main() {
@@ -34,10 +34,10 @@ int main() {
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def replay(tmp_path_factory):
     d = tmp_path_factory.mktemp("pool")
-    src, exe = d / "driver.cpp", d / "driver"
-    src.write_text(DRIVER)
+    src, exe = d / "replay.cpp", d / "replay"
+    src.write_text(REPLAY_SRC)
     subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)], check=True)
     return str(exe)
 
@@ -76,7 +76,7 @@ class FirstFit:
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_pool_matches_first_fit_model(driver, seed):
+def test_pool_matches_first_fit_model(replay, seed):
     rng = np.random.default_rng(seed)
     size = 1 << 24
     ops, model, live, expect = [f"R {size}"], FirstFit(size), [], []
@@ -95,7 +95,7 @@ def test_pool_matches_first_fit_model(driver, seed):
     for o, n in live:
         ops.append(f"F {o} {n}")
     ops.append("L")
-    out = subprocess.run([driver], input="\n".join(ops) + "\n", capture_output=True, text=True, check=True)
+    out = subprocess.run([replay], input="\n".join(ops) + "\n", capture_output=True, text=True, check=True)
     lines = out.stdout.split("\n")
     got = []
     for ln in lines[:len(expect)]:
@@ -106,7 +106,7 @@ def test_pool_matches_first_fit_model(driver, seed):
     assert (largest, blocks) == (size, 1)          # everything retired: one free block again
 
 
-def test_live_blocks_never_overlap(driver):
+def test_live_blocks_never_overlap(replay):
     rng = np.random.default_rng(9)
     size = 1 << 22
     ops, sizes = [f"R {size}"], []
@@ -114,7 +114,7 @@ def test_live_blocks_never_overlap(driver):
         n = int(rng.integers(1, 1 << 16))
         ops.append(f"A {n}")
         sizes.append(n)
-    out = subprocess.run([driver], input="\n".join(ops) + "\n", capture_output=True, text=True, check=True)
+    out = subprocess.run([replay], input="\n".join(ops) + "\n", capture_output=True, text=True, check=True)
     blocks = []
     for ln, n in zip(out.stdout.split("\n"), sizes):
         ok, off = ln.split()
