@@ -247,6 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     int4* rows = (int4*)(lds + tc.off_rows);                    // tile rows: (lds start, len, HBM start, tile start)
     unsigned* qall = (unsigned*)(lds + tc.off_q);               // per-wave hit queues
     __shared__ int s_scr[kThreads / 64];
+    __shared__ int s_unit;                                      // next home unit to hand out
     const float4* tab = nullptr;                                // species pair table (kSp)
     if constexpr (kSp) {
         __shared__ float4 s_tab[kMaxTypes * kMaxTypes];
@@ -371,6 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
         }
     }
     for (int k = tid; k < 3 * nt; k += kThreads) acc[k] = 0;
+    if (tid == 0) s_unit = nw;                          // units 0 .. nw-1 start the waves
     __syncthreads();
 
     // 4. candidates, one home unit per wave at a time: ux consecutive cells
@@ -406,12 +408,19 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     // home units (ux consecutive cells of a tile row) go to the waves in turn
     const int upr = (P0 + tc.ux - 1) / tc.ux;           // units per tile row
     const int nunits = upr * nrows;
-    int hu = wave, ry = 0, rz = 0;                      // unit within its row, row (y, z): wave-uniform
-    while (hu >= upr) { hu -= upr; if (++ry == P1) { ry = 0; ++rz; } }
-    for (int un = wave; un < nunits; un += nw) {
-        const int lx = 1 + hu * tc.ux, ly = ry + 1, lz = rz + 1;
-        hu += nw;
-        while (hu >= upr) { hu -= upr; if (++ry == P1) { ry = 0; ++rz; } }
+    // each wave takes the next unit when it is done with one (face rows
+    // cost about twice an interior row, so a fixed deal of units to waves
+    // leaves waves idle while the slowest finishes)
+    const float inv_upr = 1.0f / (float)upr;
+    auto next_unit = [&]() {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(&s_unit, 1);
+        return __builtin_amdgcn_readfirstlane(v);
+    };
+    for (int un = wave; un < nunits; un = next_unit()) {
+        const int row = small_div(un, inv_upr);         // row (y, z) of the unit, y fastest
+        const int rz = small_div(row, inv_p1), ry = row - rz * P1;
+        const int lx = 1 + (un - row * upr) * tc.ux, ly = ry + 1, lz = rz + 1;
         const int w = min(tc.ux, P0 + 1 - lx);          // cells in this unit
         const int cown = lx + S0 * (ly + S1 * lz);
         const int own_s = __builtin_amdgcn_readfirstlane(cst[cown]);
