@@ -324,7 +324,7 @@ int dpd_destroy(dpd_box box);
 
 /* Run nsteps >= 1 steps eagerly (no graph) with a HIP event pair around
  * each stage on the box stream, and return the mean device time per step of
- * each stage in ms_out[4]: binning (chunk sums, scan, scatter, gather),
+ * each stage in ms_out[4]: binning (scan, scatter, gather),
  * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate.  The steps
  * advance the box like dpd_step.  Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
