@@ -142,6 +142,33 @@ def test_cell_list_stays_stable_while_stepping():
         prev_ids = ids.copy()
 
 
+def test_cell_list_dilute_ragged_box_while_stepping():
+    """A dilute box whose cell count is not a multiple of the 64-cell
+    counters and has more counters than particles: after every step the
+    cell list equals the oracle's stable sort of the new positions taken in
+    the previous step's order, bit for bit."""
+    cells = (37, 29, 23)                     # 24 679 cells, 386 counters, 200 particles
+    pos, vel = inputs.uniform_state(cells, n=200, kT=25.0, seed=13)
+    b = _box(cells, pos, vel, dpd.make_params(a=0.0, gamma=0.5, kT=25.0, dt=0.05), 13)
+    b.build_cells()
+    prev_ids = b.read_raw()[0][:, 3].view(np.int32).copy()
+    moved = 0
+    for step in range(12):
+        b.step(1)
+        p4, _, cs = b.read_raw()
+        ids = p4[:, 3].view(np.int32)
+        by_id = np.empty((len(ids), 3), np.float32)
+        by_id[ids] = p4[:, :3]
+        order, start = oracle.bin_cells(by_id[prev_ids], cells)
+        np.testing.assert_array_equal(cs, start, err_msg=f"step {step}")
+        np.testing.assert_array_equal(ids, prev_ids[order], err_msg=f"step {step}")
+        moved += int(np.any(ids != prev_ids))
+        prev_ids = ids.copy()
+    assert b.stats()["escaped"] == 0
+    assert moved > 0                          # the order did change along the way
+    b.close()
+
+
 # ---------------------------------------------------------------------------
 # forces and one step
 # ---------------------------------------------------------------------------
