@@ -14,9 +14,11 @@
 //                  with the periodic image shift applied on the way in).  Each
 //                  tile particle walks the half stencil: forward neighbour
 //                  cells, later particles of its own cell, and backward cells
-//                  that lie in the halo.  Candidates with r < r_c are
-//                  compacted into a per-wave queue (ballot + popcount) and
-//                  evaluated 64 at a time with every lane busy.  Both halves
+//                  that lie in the halo.  Home units (one or two cells of a
+//                  tile row) go to the waves from an LDS counter as the waves
+//                  free up.  Candidates with r < r_c are compacted into a
+//                  per-wave queue (ballot + popcount) and evaluated 64 at a
+//                  time with every lane busy.  Both halves
 //                  of a pair inside the tile are accumulated (F_ij to i,
 //                  -F_ij to j); a pair that crosses the tile boundary is
 //                  evaluated once from each side and only the tile particle is
