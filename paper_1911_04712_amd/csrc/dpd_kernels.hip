@@ -471,8 +471,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
     const float4 x = d.pos_a[i], v = d.vel_a[i];     // in flight during the rank search
     const int c = d.keyslot[i].x;
     const int s = d.cell_start[c], e = d.cell_start[c + 1];
+    // the first eight members in one round of independent loads (a cell
+    // rarely holds more), then the rest one by one
     int rank = 0;
-    for (int t = s; t < e; ++t) rank += perm[t] < i;
+    const int last = d.n - 1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int o = perm[min(s + k, last)];
+        rank += (s + k < e && o < i) ? 1 : 0;
+    }
+    for (int t = s + 8; t < e; ++t) rank += perm[t] < i;
     d.pos_b[s + rank] = x;
     d.vel_b[s + rank] = v;
 }
