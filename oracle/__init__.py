@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liborc.so")
+# DPD_ORACLE_SANITIZED=1 selects the ASan/UBSan build (see oracle/build.py)
+_SANITIZED = os.environ.get("DPD_ORACLE_SANITIZED", "") == "1"
+_LIB_PATH = os.path.join(_HERE, "liborc_san.so" if _SANITIZED else "liborc.so")
 _lib = None
 
 
@@ -42,7 +44,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             from . import build
-            build.build()
+            build.build(sanitize=_SANITIZED)
         L = ctypes.CDLL(_LIB_PATH)
         u32p, u64p, i64p, i32p = (ctypes.POINTER(t) for t in
                                   (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32))

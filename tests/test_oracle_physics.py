@@ -10,6 +10,9 @@
   - periodic Poiseuille flow (Sec. 4.2, Eq. 11): antisymmetric two-half
     parabola, with the viscosity of the Groot-Warren fluid of Table 1
     (a = 25, gamma = 6.75, rho = 3, kT = 1, dt = 0.04: eta = 0.91);
+  - the degrees of freedom of kT: two particles whose momentum sum stays
+    zero carry heat in their relative motion only, so kT_centred must
+    average to kT with 3 (N - 1) = 3 degrees of freedom;
   - kernel exponent k (w_R = w^k, w_D = w_R^2, Sec. 2.1): the equilibrium
     temperature stays kT at k = 1/4 (the fluctuation-dissipation pairing of
     the two kernels), and the pressure's mean-field limit stays pi / 30
@@ -55,6 +58,35 @@ def test_half_step_estimator_is_biased_up(equilibrium_run):
     n = 1536
     kt_half = 2.0 * equilibrium_run["ke_half"] / (3.0 * (n - 1))
     assert kt_half.mean() > equilibrium_run["kT_centred"].mean()
+
+
+def test_two_particle_equipartition_counts_3_of_6_degrees():
+    """Two particles in a 3^3 box, thermostatted by the pair force alone
+    (a = 0): their momentum sum never changes, so only the relative motion
+    (3 of the 6 velocity components) holds heat, and equipartition puts
+    kT/2 on each of those.  The time-centred estimate must average to kT; a
+    count of 3 N = 6 degrees of freedom would give kT/2, and 3 (N + 1) = 9
+    kT/3.  Twenty blocks of 60 000 steps after a discarded first one."""
+    rng = np.random.default_rng(3)
+    x = rng.random((2, 3)) * 3.0
+    v = rng.normal(size=(2, 3))
+    v -= v.mean(axis=0)
+    ids = np.arange(2, dtype=np.uint32)
+    p = oracle.make_params(a=0.0, gamma=4.5, kT=1.0, dt=0.01)
+    blocks = []
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)           # two particles: a thread team per step would only cost time
+    try:
+        for k in range(21):
+            diag, _, _, _ = oracle.step(x, v, ids, (3, 3, 3), p, seed=5, step0=60000 * k, nsteps=60000)
+            blocks.append(diag["kT_centred"].mean())
+            np.testing.assert_allclose(diag["momentum"][-1], 0.0, atol=1e-12)   # no net momentum, ever
+    finally:
+        oracle.set_num_threads(threads)
+    m = np.mean(blocks[1:])
+    se = np.std(blocks[1:], ddof=1) / math.sqrt(20)
+    assert abs(m - 1.0) < 0.15, (m, se)
+    assert abs(m - 1.0) < 4 * se + 0.02, (m, se)
 
 
 def _eos_alpha(cells, rho, a, seed, nsteps=3000, discard=500):

@@ -38,7 +38,11 @@ def replay(tmp_path_factory):
     d = tmp_path_factory.mktemp("pool")
     src, exe = d / "replay.cpp", d / "replay"
     src.write_text(REPLAY_SRC)
-    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    # built with AddressSanitizer and UndefinedBehaviorSanitizer: every replay
+    # below also checks the allocator for out-of-bounds access, use after free
+    # and undefined behaviour
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                    "-fno-omit-frame-pointer", "-I", CSRC, str(src), "-o", str(exe)], check=True)
     return str(exe)
 
 
