@@ -191,6 +191,7 @@ def bench_species(w, steps=500, warmup=30, sample=4096, check=True):
     box.set_types(types)
     tile = list(box.tune_tile(reps=5)[0])
     box.step(warmup)
+    box.prepare(steps)                  # graphs captured outside the timed region
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -233,6 +234,9 @@ def stage_roofline(n, stage):
     and integrate stages (HBM-bound by their byte counts)."""
     out = {}
     for name, per in (("bin", BIN_BYTES), ("integrate", INTEGRATE_BYTES)):
+        if stage[name] <= 0.0:          # the kick-drift runs inside the force kernel
+            out[name] = "fused into the force kernel"
+            continue
         gbps = n * per / (stage[name] / 1e3) / 1e9
         out[name] = {"bytes_per_particle": per, "GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
     return out
@@ -255,6 +259,7 @@ def bench_large(steps=50, warmup=5):
     del pos, vel
     tile = list(box.tune_tile(reps=2)[0])
     box.step(warmup)
+    box.prepare(steps)                  # graphs captured outside the timed region
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -291,6 +296,7 @@ def bench_paper_pp64(steps=200, warmup=10):
     del pos, vel
     tile = list(box.tune_tile(reps=3)[0])
     box.step(warmup)
+    box.prepare(steps)                  # graphs captured outside the timed region
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -328,6 +334,7 @@ def bench_walls(steps=500, warmup=30, R=20.0, length=48):
     box.set_frozen(frozen)
     tile = list(box.tune_tile(reps=5)[0])
     box.step(warmup)
+    box.prepare(steps)                  # graphs captured outside the timed region
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -414,6 +421,53 @@ def bench_served(nreq=1000, quantum=50, pool_gb=32, max_slots=256):
             "speedup_vs_fifo": makespan_f / makespan}
 
 
+CPU_BUDGET = 6.6e7     # oracle particle-steps of the all-core sample at rho = 3 (about 10-15 s on 16 threads)
+
+
+def cpu_baseline(w, pos, vel, max_steps):
+    """The oracle's throughput on the host cores, on a bounded sample of the
+    workload: the whole box for as many steps as the budget allows (at least
+    one), on every core; and on one thread, a smaller box of the same fluid
+    (same density and parameters) for a few steps."""
+    import numpy as np
+    import oracle
+    from paper_1911_04712_amd import inputs
+    n = w.n
+    rho = n / float(w.cells[0] * w.cells[1] * w.cells[2])
+    op = oracle.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass, body_f=w.body_f)
+    steps = int(max(1, min(max_steps, round(CPU_BUDGET * 3.0 / rho / n))))
+    x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    ids = np.arange(n, dtype=np.uint32)
+    c0 = time.perf_counter()
+    oracle.step(x, v, ids, w.cells, op, w.seed, 0, steps, nbins=w.profile_bins, want_diag=True)
+    cs = time.perf_counter() - c0
+    cores = oracle.num_threads()
+    out = {"value": n * steps / cs, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} steps of the same {w.name} box ({n} particles), {cs:.1f} s on {cores} threads"}
+    # one thread: 8 steps of a box of the same fluid sized to about 1/16 of
+    # the budget (the workload's own box when that is smaller)
+    side = max(3, int(round((CPU_BUDGET / 16.0 * 3.0 / rho / 8.0 / rho) ** (1.0 / 3.0))))
+    if side ** 3 >= w.cells[0] * w.cells[1] * w.cells[2]:
+        sub, n1, p1, v1 = tuple(w.cells), n, pos, vel
+        what = f"the same {w.name} box ({n} particles)"
+    else:
+        sub = (side, side, side)
+        n1 = int(round(rho * side ** 3))
+        p1, v1 = inputs.uniform_state(sub, n=n1, kT=w.kT, seed=w.seed)
+        what = f"a {side}^3 box of the same fluid (rho = {rho:g}, {n1} particles)"
+    x1, u1 = p1.astype(np.float64).copy(), v1.astype(np.float64).copy()
+    oracle.set_num_threads(1)
+    try:
+        c0 = time.perf_counter()
+        oracle.step(x1, u1, np.arange(n1, dtype=np.uint32), sub, op, w.seed, 0, 8, nbins=0, want_diag=True)
+        c1 = time.perf_counter() - c0
+    finally:
+        oracle.set_num_threads(cores)
+    out["single_thread"] = {"value": n1 * 8 / c1, "unit": "particle-steps/s", "cores": 1,
+                            "sample": f"8 steps of {what}, {c1:.1f} s on 1 thread"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,9 +475,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cube48_rho3")
     ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage with HIP events")
+    ap.add_argument("--force-reps", type=int, default=20, help="force-kernel launches timed back to back")
     ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default cell tile of the force kernel")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1911_04712_amd", "tune_cache_gfx950.json"),
+                    help="autotuner cache file ('' for none): tuned tiles are reused, new ones added")
     ap.add_argument("--tile", default="", help="cell tile of the force kernel, e.g. 6,3,3 (no autotuning)")
     ap.add_argument("--threads", type=int, default=0, help="force-kernel workgroup size with --tile (256/512/1024)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched measurement")
@@ -451,18 +508,25 @@ def main():
     params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass, body_f=w.body_f,
                              profile_bins=w.profile_bins)
     torch.cuda.set_device(0)
+    dpd.set_tune_cache(args.tune_cache or None)
     box = dpd.Box(w.cells, n, params=params, seed=w.seed)
     box.set_state(pos, vel)
     # the autotuner picks the force kernel's cell tile on this machine (setup,
     # outside the timed region; tiles never change results)
+    t_tune = 0.0
     if args.tile:
         box.set_tile(tuple(int(t) for t in args.tile.split(",")))
         box.set_force_threads(args.threads)
         tile = list(box.get_tile())
     else:
+        t_tune = time.perf_counter()
         tile = list(box.tune_tile(reps=5)[0]) if not args.no_tune else list(box.get_tile())
+        t_tune = time.perf_counter() - t_tune
 
     box.step(args.warmup)
+    # the HIP graphs of the timed run are captured here, outside the timed
+    # region, whatever the warm-up length
+    box.prepare(args.steps)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -479,16 +543,26 @@ def main():
         sys.exit(1)
     value = n * args.steps / (ms / 1e3)
 
-    # per-stage device time (HIP events around eager launches on the box stream)
+    # per-stage device time (HIP events around each stage of eager steps on
+    # the box stream); the force stage is the step's force kernel, which also
+    # integrates (kick-drift fused into its write-out)
     stage = box.profile_steps(args.profile_steps)
     f_ms = stage["force"]
+    # the same kernel without the fused kick-drift, launched back to back
+    # between two HIP events on the state the run reached (forces only)
+    f_only_ms = box.time_force(reps=args.force_reps)
     ops = force_ops(n, rho)
     achieved = ops / (f_ms / 1e3) / 1e12
-    force_bytes = n * (32.0 + 16.0) + (n / rho) * 4.0
+    # algorithmic HBM bytes of the fused kernel: pos, vel read (32 B), force
+    # written (16 B), cell starts (4 / rho B), and the kick-drift's pos, vel and
+    # (cell, slot) written (40 B)
+    force_bytes = n * (32.0 + 16.0 + 40.0) + (n / rho) * 4.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(w.name),
-                "kernel": "k_force_tiled", "kernel_ms": round(f_ms, 4),
-                "hbm_algorithmic_GBps": round(force_bytes / (f_ms / 1e3) / 1e9, 1)}
+                "kernel": "k_force_tiled (pair forces with the kick-drift fused)", "kernel_ms": round(f_ms, 4),
+                "hbm_algorithmic_GBps": round(force_bytes / (f_ms / 1e3) / 1e9, 1),
+                "force_only_kernel_ms": round(f_only_ms, 4),
+                "force_only_frac": round(ops / (f_only_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)}
 
     out = {"metric": "particle-steps/s DPD (1 GPU)", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
@@ -501,6 +575,8 @@ def main():
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
            "stages_hbm": stage_roofline(n, stage),
            "wall_s": round(wall, 3),
+           "autotune_s": round(t_tune, 3),
+           "tune_cache": os.path.relpath(args.tune_cache, ROOT) if args.tune_cache else None,
            "roofline": roofline,
            "env": run_env()}
 
@@ -525,23 +601,13 @@ def main():
             "ke_half_rel_err": float(abs(sg["ke_half"] - rec["ke_half"][0]) / rec["ke_half"][0]),
             "kT_centred_rel_err": float(abs(sg["kT_centred"] - rec["kT_centred"][0]) / rec["kT_centred"][0]),
         }
-        sample_steps = args.cpu_steps
-        x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
-        ids = np.arange(n, dtype=np.uint32)
-        op = oracle.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, mass=w.mass, body_f=w.body_f)
-        c0 = time.perf_counter()
-        oracle.step(x, v, ids, w.cells, op, w.seed, 0, sample_steps, nbins=w.profile_bins, want_diag=True)
-        cs = time.perf_counter() - c0
-        out["cpu_baseline"] = {"value": n * sample_steps / cs, "unit": "particle-steps/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": f"{sample_steps} steps of the same {w.name} box ({n} particles), "
-                                         f"{cs:.1f} s"}
+        out["cpu_baseline"] = cpu_baseline(w, pos, vel, args.cpu_steps)
     box.close()
     if not args.no_species:
         out["species"] = bench_species(w, check=not args.no_cpu_baseline)
     if not args.no_walls:
         out["walls"] = bench_walls()
-    if not args.no_large:
+    if not args.no_large and w.name != "pp192x96x96_rho8":
         out["large"] = bench_large()
         out["paper_pp64"] = bench_paper_pp64()
     if not args.no_batched:

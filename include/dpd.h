@@ -109,7 +109,8 @@ typedef struct dpd_box_s* dpd_box;
 typedef struct {
     int32_t cells[3];
     int32_t reserved;     /* must be 0 */
-    int64_t n;            /* 0 <= n <= 2^30 */
+    int64_t n;            /* 0 <= n <= 715 827 882 ((2^31 - 1) / 3: row offsets
+                             3 i of the n x 3 arrays stay 32-bit)            */
 } dpd_geom;
 
 /* Model parameters (Sec. 2.1, Eqs. 3-5; Sec. 4.2, Eq. 11).
@@ -264,6 +265,19 @@ int dpd_get_force_threads(dpd_box box, int32_t* threads);
  * changes.  Synchronises. */
 int dpd_tune_tile(dpd_box box, int32_t reps, int32_t tile_out[3], double* ms_out);
 
+/* Autotuner cache: a JSON file (path NULL or "" turns the cache off) that
+ * dpd_tune_tile and dpd_batch_tune consult before timing anything.  Entries
+ * are keyed by the GPU architecture, the revision of the force kernel's
+ * sources the library was built from, and the box (cells, particles per
+ * occupied cell, species table on or off, kernel exponent k = 1 or not) or,
+ * for a batch, the list of its boxes with their own tile requests.  A hit
+ * applies the stored tile and workgroup size (if they still fit a CU's LDS)
+ * without timing and reports the stored ms; a miss times as usual and adds
+ * the winner to the file (rewritten whole; an unwritable place keeps the
+ * entries in memory only).  Process-wide; thread-safe.  Results never depend
+ * on the tile, so the cache changes speed only. */
+int dpd_set_tune_cache(const char* path);
+
 /* Set the 64-bit seed of the random term. */
 int dpd_set_seed(dpd_box box, uint64_t seed);
 
@@ -297,6 +311,22 @@ int dpd_build_cells(dpd_box box);
  * params, seed and state.  Asynchronous. */
 int dpd_step(dpd_box box, int64_t nsteps);
 
+/* Capture, without running anything, the HIP graphs that dpd_step(box,
+ * nsteps) would launch now (runs are replayed graphs of up to 64 steps plus
+ * one graph of the remainder; the last few lengths stay cached until the
+ * tile, flags or kernel choice change), so that a later dpd_step of that
+ * length spends no time capturing.  Requires params, seed and state.
+ * DPD_EDEVICE if a capture fails. */
+int dpd_prepare_steps(dpd_box box, int64_t nsteps);
+
+/* Time the pair-force kernel alone: `reps` (1..10000) back-to-back launches
+ * on the box stream between two HIP events, after one untimed launch; *ms_out
+ * is the mean ms per launch.  The forces are those of the current positions
+ * (binned first if needed); the state does not advance, and afterwards the
+ * box holds the cell list of its current state as after dpd_build_cells.
+ * Synchronises. */
+int dpd_time_force(dpd_box box, int32_t reps, double* ms_out);
+
 /* Copy one quantity (DPD_POS, DPD_VEL, DPD_VEL_CENTRED, DPD_FORCE) to
  * out_n3 (n x 3 floats, row = id).  DPD_FORCE and DPD_VEL_CENTRED need at
  * least one step.  Synchronises. */
@@ -325,8 +355,9 @@ int dpd_destroy(dpd_box box);
 /* Run nsteps >= 1 steps eagerly (no graph) with a HIP event pair around
  * each stage on the box stream, and return the mean device time per step of
  * each stage in ms_out[4]: binning (scan, scatter, gather),
- * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate.  The steps
- * advance the box like dpd_step.  Synchronises. */
+ * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate (the fold of the
+ * reductions, which a graph runs inside the next step's scan, runs after the
+ * timed stages).  The steps advance the box like dpd_step.  Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
 
 /* ---- batches of independent boxes ------------------------------------------

@@ -26,13 +26,28 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
+# Sources whose revision keys the autotuner cache: a tile tuned for one
+# version of the force kernel is not reused for another.
+REV_SOURCES = ["dpd_force.hip", "dpd_device.hpp", "dpd_internal.hpp"]
+
+
+def kernel_rev() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in REV_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
+    rev = kernel_rev()
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC, *extra,
+               "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC, f'-DDPD_KERNEL_REV="{rev}"', *extra,
                "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -13,6 +13,8 @@
 #include <cstring>
 #include <new>
 #include <array>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "dpd.h"
@@ -48,7 +50,8 @@ bool geom_ok(const dpd_geom* g)
     for (int k = 0; k < 3; ++k)
         if (g->cells[k] < 3 || g->cells[k] > 4096) return false;
     const int64_t nc = (int64_t)g->cells[0] * g->cells[1] * g->cells[2];
-    return g->n >= 0 && g->n <= (int64_t(1) << 30) && nc < (int64_t(1) << 31) - 1;
+    // 3 n < 2^31: the n x 3 row arrays are indexed with 32-bit offsets
+    return g->n >= 0 && g->n <= ((int64_t(1) << 31) - 1) / 3 && nc < (int64_t(1) << 31) - 1;
 }
 
 // Spacing of FP32 numbers at L_max: 2^(floor(log2 L_max) - 23).
@@ -61,7 +64,7 @@ double grid_of(const dpd_geom* g)
     return std::ldexp(1.0, e - 23);
 }
 
-constexpr int kGraphSteps = 8;          // steps per captured graph of a single box
+constexpr int kGraphMax = 64;           // steps per captured graph of a single box (longer runs replay it)
 constexpr int kBatchGraphMax = 1024;    // a batch run of up to this many steps is one graph launch
 constexpr int kBatchGraphMin = 64;      // shorter batch runs are launched directly (no capture)
 constexpr size_t kLdsLimit = 160 * 1024 - 1280;  // LDS per CU less the kernels' static LDS
@@ -98,7 +101,9 @@ Layout make_layout(int64_t n, int64_t nc)
     L.count = take((size_t)nc * sizeof(int));
     L.cell_start = take((size_t)(nc + 1) * sizeof(int));
     L.bsum = take((size_t)((nc + kSubChunk - 1) / kSubChunk) * sizeof(int));
-    L.partials = take((size_t)kIntegrateMaxBlocks * kPartials * sizeof(double));
+    // one partial per integrate block, or per force tile when the kick-drift
+    // is fused into the force kernel (a tile holds at least one cell)
+    L.partials = take((size_t)std::max<int64_t>(kIntegrateMaxBlocks, nc) * kPartials * sizeof(double));
     L.profile = take((size_t)kProfileMaxBins * 2 * sizeof(long long));
     L.stats = take(sizeof(DevStats));
     L.flags = take(4 * sizeof(int));
@@ -109,6 +114,53 @@ Layout make_layout(int64_t n, int64_t nc)
 }
 
 }  // namespace dpd
+
+namespace {
+
+// Captured multi-step graphs of one launch group, kept by run length (a few
+// lengths, least recently used first out).  Each graph holds its steps and
+// the final fold of the reductions, so a run is complete when it returns.
+struct GraphCache {
+    static constexpr int kSlots = 4;
+    struct Slot {
+        int64_t steps = 0;
+        hipGraphExec_t exec = nullptr;
+        uint64_t used = 0;
+    } slot[kSlots];
+    hipStream_t cap = nullptr;
+    uint64_t tick = 0;
+
+    void clear()
+    {
+        for (Slot& s : slot) {
+            if (s.exec) (void)hipGraphExecDestroy(s.exec);
+            s = Slot{};
+        }
+    }
+    void release()
+    {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+        cap = nullptr;
+    }
+    Slot* find(int64_t steps)
+    {
+        for (Slot& s : slot)
+            if (s.exec && s.steps == steps) return &s;
+        return nullptr;
+    }
+    Slot* victim()
+    {
+        Slot* v = &slot[0];
+        for (Slot& s : slot) {
+            if (!s.exec) return &s;
+            if (s.used < v->used) v = &s;
+        }
+        return v;
+    }
+};
+
+}  // namespace
 
 struct dpd_box_s {
     dpd_geom geom{};
@@ -149,9 +201,8 @@ struct dpd_box_s {
     int n_frozen = 0;          // frozen wall particles of the current state
     double rho_occ = 0.0;      // particles per occupied cell of the loaded state (0: use n / nc)
 
-    // captured multi-step graph
-    hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
+    // captured multi-step graphs (dropped when the launch shape changes)
+    GraphCache graphs;
     bool graph_dirty = true;
 };
 
@@ -162,9 +213,8 @@ struct dpd_batch_s {
     int* d_pre = nullptr;
     std::vector<int> pre;      // host copy [kNumWork][nbox + 1]
     dpd::LaunchPlan lp{};
-    hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int64_t graph_steps = 0;
+    GraphCache graphs;
+    bool graph_dirty = true;
     hipEvent_t done = nullptr;
 };
 
@@ -320,11 +370,16 @@ int push_desc(dpd_box_s* b)
     b->lp.force_threads = d.tc.threads;
     b->lp.any_virial = (d.flags & DPD_FLAG_VIRIAL) != 0;
     b->lp.reference_force = (d.flags & DPD_FLAG_REFERENCE_FORCE) != 0;
-    b->lp.species = d.fc.ntypes > 1;
+    // the species instantiation also carries the species of particles that
+    // have one while the box is back to one species from the params (same
+    // forces: every table entry is then that one pair)
+    b->lp.species = d.fc.ntypes > 1 || b->max_type > 0;
     b->lp.walls = d.sc.wall_kind != 0 || b->n_frozen > 0;
+    b->lp.fuse = !b->lp.walls && !b->lp.reference_force;
     // a captured graph holds the kernel choice and the launch shapes
     if (old.lds_force != b->lp.lds_force || old.any_virial != b->lp.any_virial ||
         old.reference_force != b->lp.reference_force || old.species != b->lp.species || old.walls != b->lp.walls ||
+        old.fuse != b->lp.fuse ||
         old.force_threads != b->lp.force_threads)
         b->graph_dirty = true;
     for (int k = 0; k < dpd::kNumWork; ++k) b->graph_dirty |= old.total[k] != b->lp.total[k];
@@ -337,9 +392,9 @@ int push_desc(dpd_box_s* b)
 
 hipError_t enqueue_step_tail(const dpd::LaunchPlan& lp, hipStream_t s)
 {
-    hipError_t e = dpd::launch_force(lp, s);
+    hipError_t e = dpd::launch_force(lp, s, true);
     if (e == hipSuccess) e = dpd::launch_virial(lp, s);
-    if (e == hipSuccess) e = dpd::launch_integrate(lp, s);
+    if (e == hipSuccess && !lp.fuse) e = dpd::launch_integrate(lp, s);
     return e;
 }
 
@@ -353,16 +408,15 @@ hipError_t enqueue_steps(const dpd::LaunchPlan& lp, int64_t nsteps, hipStream_t 
     return e;
 }
 
+// Capture nsteps steps and the final fold of the reductions as one graph.
 int capture(const dpd::LaunchPlan& lp, int64_t nsteps, hipStream_t* cap, hipGraphExec_t* exec)
 {
-    if (*exec) {
-        (void)hipGraphExecDestroy(*exec);
-        *exec = nullptr;
-    }
+    *exec = nullptr;
     if (!*cap) HIPCHK(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(*cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_steps(lp, nsteps, *cap);
+    if (e == hipSuccess) e = dpd::launch_fold(lp, *cap);
     hipError_t e2 = hipStreamEndCapture(*cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -370,8 +424,52 @@ int capture(const dpd::LaunchPlan& lp, int64_t nsteps, hipStream_t* cap, hipGrap
     }
     e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(DPD_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        *exec = nullptr;
+        return fail(DPD_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
     return DPD_OK;
+}
+
+// The graph of a run of `steps` steps: from the cache, else captured (the
+// least recently used length makes room).  `dirty` drops every cached graph
+// first (the launch shape changed).
+int graph_for(GraphCache& gc, bool& dirty, const dpd::LaunchPlan& lp, int64_t steps, hipGraphExec_t* out)
+{
+    if (dirty) {
+        gc.clear();
+        dirty = false;
+    }
+    GraphCache::Slot* s = gc.find(steps);
+    if (!s) {
+        s = gc.victim();
+        if (s->exec) (void)hipGraphExecDestroy(s->exec);
+        *s = GraphCache::Slot{};
+        hipGraphExec_t ex = nullptr;
+        const int rc = capture(lp, steps, &gc.cap, &ex);
+        if (rc) return rc;
+        s->steps = steps;
+        s->exec = ex;
+    }
+    s->used = ++gc.tick;
+    *out = s->exec;
+    return DPD_OK;
+}
+
+// How dpd_step runs n steps after its optional first step: `full` graphs of
+// `g` steps, then one graph of `tail` steps.
+struct RunPlan {
+    int64_t g = 0, full = 0, tail = 0;
+};
+
+RunPlan plan_run(int64_t n, int64_t gmax)
+{
+    RunPlan p;
+    if (n <= 0) return p;
+    p.g = n < gmax ? n : gmax;
+    p.full = n / p.g;
+    p.tail = n - p.full * p.g;
+    return p;
 }
 
 int sync_box(dpd_box_s* b)
@@ -383,6 +481,139 @@ int sync_box(dpd_box_s* b)
 hipMemcpyKind kind_to(int where) { return where == DPD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 
 bool ready(const dpd_box_s* b) { return b->have_params && b->have_seed && b->have_state; }
+
+// ---- autotuner cache ----------------------------------------------------------
+// A JSON file of tuned (tile, workgroup size) per key: the GPU architecture,
+// the revision of the force kernel's sources (fixed at build time), and the
+// box geometry, density and kernel variant, or a batch's list of those.
+// One entry per line, written and read by the two functions below.
+#ifndef DPD_KERNEL_REV
+#define DPD_KERNEL_REV "dev"
+#endif
+
+struct TuneEntry {
+    std::string key;
+    int tile[3] = {0, 0, 0};
+    int threads = 0;
+    double ms = 0.0;
+};
+
+struct TuneCacheFile {
+    std::mutex mu;
+    std::string path;                 // empty: no cache
+    std::vector<TuneEntry> entries;
+};
+
+TuneCacheFile& tune_file()
+{
+    static TuneCacheFile f;
+    return f;
+}
+
+void tune_read(TuneCacheFile& f)
+{
+    f.entries.clear();
+    FILE* fp = std::fopen(f.path.c_str(), "r");
+    if (!fp) return;
+    char line[8192];
+    while (std::fgets(line, sizeof line, fp)) {
+        const char* k = std::strstr(line, "\"key\": \"");
+        const char* t = std::strstr(line, "\"tile\": [");
+        const char* h = std::strstr(line, "\"threads\": ");
+        const char* m = std::strstr(line, "\"ms\": ");
+        if (!k || !t || !h || !m) continue;
+        k += 8;
+        const char* ke = std::strchr(k, '"');
+        if (!ke) continue;
+        TuneEntry e;
+        e.key.assign(k, ke);
+        if (std::sscanf(t + 9, "%d, %d, %d", &e.tile[0], &e.tile[1], &e.tile[2]) != 3) continue;
+        if (std::sscanf(h + 11, "%d", &e.threads) != 1 || std::sscanf(m + 6, "%lf", &e.ms) != 1) continue;
+        f.entries.push_back(e);
+    }
+    std::fclose(fp);
+}
+
+void tune_write(const TuneCacheFile& f)
+{
+    const std::string tmp = f.path + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;                  // a read-only place: the cache stays in memory
+    std::fprintf(fp, "{\"dpd_tune_cache\": 1, \"entries\": [\n");
+    for (size_t i = 0; i < f.entries.size(); ++i) {
+        const TuneEntry& e = f.entries[i];
+        std::fprintf(fp, "  {\"key\": \"%s\", \"tile\": [%d, %d, %d], \"threads\": %d, \"ms\": %.6g}%s\n",
+                     e.key.c_str(), e.tile[0], e.tile[1], e.tile[2], e.threads, e.ms,
+                     i + 1 < f.entries.size() ? "," : "");
+    }
+    std::fprintf(fp, "]}\n");
+    const bool ok = std::fclose(fp) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), f.path.c_str());
+}
+
+bool tune_lookup(const std::string& key, TuneEntry* out)
+{
+    TuneCacheFile& f = tune_file();
+    std::lock_guard<std::mutex> lk(f.mu);
+    if (f.path.empty()) return false;
+    for (const TuneEntry& e : f.entries)
+        if (e.key == key) {
+            *out = e;
+            return true;
+        }
+    return false;
+}
+
+void tune_store(const std::string& key, const int tile[3], int threads, double ms)
+{
+    TuneCacheFile& f = tune_file();
+    std::lock_guard<std::mutex> lk(f.mu);
+    if (f.path.empty()) return;
+    tune_read(f);                     // another process may have added entries
+    TuneEntry e;
+    e.key = key;
+    for (int k = 0; k < 3; ++k) e.tile[k] = tile[k];
+    e.threads = threads;
+    e.ms = ms;
+    bool found = false;
+    for (TuneEntry& x : f.entries)
+        if (x.key == key) {
+            x = e;
+            found = true;
+        }
+    if (!found) f.entries.push_back(e);
+    tune_write(f);
+}
+
+bool tune_cache_on()
+{
+    TuneCacheFile& f = tune_file();
+    std::lock_guard<std::mutex> lk(f.mu);
+    return !f.path.empty();
+}
+
+std::string arch_name(hipStream_t)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// The part of a key that describes one box: what the kernel's speed depends on.
+std::string box_tune_part(const dpd_box_s* b)
+{
+    char buf[160];
+    const double rho = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
+    const double rho_t = b->rho_occ > 1.1 * rho ? b->rho_occ : rho;
+    std::snprintf(buf, sizeof buf, "%dx%dx%d/rho%.2f/sp%d/kg%d", b->cells[0], b->cells[1], b->cells[2], rho_t,
+                  b->hd.fc.ntypes > 1 ? 1 : 0, b->hd.fc.pc.kgen);
+    return buf;
+}
+
+std::string tune_key_prefix(hipStream_t s) { return arch_name(s) + "|" DPD_KERNEL_REV "|"; }
 
 }  // namespace
 
@@ -409,7 +640,7 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
 {
     if (!out) return fail(DPD_EINVAL, "dpd_create: null output");
     *out = nullptr;
-    if (!geom_ok(geom)) return fail(DPD_EINVAL, "dpd_create: invalid geometry (cells >= 3, 0 <= n <= 2^30)");
+    if (!geom_ok(geom)) return fail(DPD_EINVAL, "dpd_create: invalid geometry (cells in 3..4096, 0 <= n <= (2^31 - 1) / 3)");
     if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(DPD_EINVAL, "dpd_create: workspace null or not 256-byte aligned");
     const int64_t nc = (int64_t)geom->cells[0] * geom->cells[1] * geom->cells[2];
     const dpd::Layout lay = dpd::make_layout(geom->n, nc);
@@ -555,7 +786,8 @@ int dpd_set_types(dpd_box b, const int32_t* type_host)
     if (b->binned || b->have_force)     // pos_b / vel_b hold a copy of the state in cell order
         HIPCHK(dpd::launch_set_types(d.pos_b, d.vel_b, b->n, staged, b->stream));
     b->max_type = mx;
-    return sync_box(b);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return push_desc(b);                // the kernel instantiation follows the species present
 }
 
 int dpd_get_types(dpd_box b, int32_t* type_host)
@@ -760,24 +992,46 @@ int dpd_step(dpd_box b, int64_t nsteps)
     if (nsteps < 0) return fail(DPD_EINVAL, "dpd_step: nsteps < 0");
     if (!ready(b)) return fail(DPD_ESTATE, "dpd_step: set params, seed and state first");
     if (nsteps == 0) return DPD_OK;
-    int64_t left = nsteps;
+    // the graphs first: a failed capture leaves the box as it was
+    const int64_t left = nsteps - (b->binned ? 1 : 0);
+    const RunPlan rp = plan_run(left, kGraphMax);
+    hipGraphExec_t gfull = nullptr, gtail = nullptr;
+    if (rp.full) {
+        const int rc = graph_for(b->graphs, b->graph_dirty, b->lp, rp.g, &gfull);
+        if (rc) return rc;
+    }
+    if (rp.tail) {
+        const int rc = graph_for(b->graphs, b->graph_dirty, b->lp, rp.tail, &gtail);
+        if (rc) return rc;
+    }
     if (b->binned) {                      // first step reuses the existing cell list
         HIPCHK(enqueue_step_tail(b->lp, b->stream));
         b->binned = false;
-        --left;
+        if (left == 0) HIPCHK(dpd::launch_fold(b->lp, b->stream));   // its reductions
     }
-    if (left >= kGraphSteps) {
-        if (b->graph_dirty || !b->graph) {
-            const int rc = capture(b->lp, kGraphSteps, &b->cap_stream, &b->graph);
-            if (rc) return rc;
-            b->graph_dirty = false;
-        }
-        for (; left >= kGraphSteps; left -= kGraphSteps) HIPCHK(hipGraphLaunch(b->graph, b->stream));
-    }
-    HIPCHK(enqueue_steps(b->lp, left, b->stream));
-    HIPCHK(dpd::launch_fold(b->lp, b->stream));   // the last step's reductions
+    for (int64_t k = 0; k < rp.full; ++k) HIPCHK(hipGraphLaunch(gfull, b->stream));
+    if (rp.tail) HIPCHK(hipGraphLaunch(gtail, b->stream));
     b->keys_valid = true;
     b->have_force = true;
+    return DPD_OK;
+}
+
+int dpd_prepare_steps(dpd_box b, int64_t nsteps)
+{
+    if (!b) return fail(DPD_EINVAL, "dpd_prepare_steps: null box");
+    if (nsteps < 0) return fail(DPD_EINVAL, "dpd_prepare_steps: nsteps < 0");
+    if (!ready(b)) return fail(DPD_ESTATE, "dpd_prepare_steps: set params, seed and state first");
+    const int64_t left = nsteps - (b->binned && nsteps > 0 ? 1 : 0);
+    const RunPlan rp = plan_run(left, kGraphMax);
+    hipGraphExec_t g = nullptr;
+    if (rp.full) {
+        const int rc = graph_for(b->graphs, b->graph_dirty, b->lp, rp.g, &g);
+        if (rc) return rc;
+    }
+    if (rp.tail) {
+        const int rc = graph_for(b->graphs, b->graph_dirty, b->lp, rp.tail, &g);
+        if (rc) return rc;
+    }
     return DPD_OK;
 }
 
@@ -795,15 +1049,19 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
         if (e == hipSuccess && !b->binned) e = dpd::launch_bin(b->lp, b->stream);
         b->binned = false;
         if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
-        if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream);
+        if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream, true);
         if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
         if (e == hipSuccess) e = dpd::launch_virial(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
-        if (e == hipSuccess) e = dpd::launch_integrate(b->lp, b->stream);
-        if (e == hipSuccess) e = dpd::launch_fold(b->lp, b->stream);
+        if (e == hipSuccess && !b->lp.fuse) e = dpd::launch_integrate(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4], b->stream);
+        // the reductions' fold normally rides in the next step's scan: here
+        // it runs after the timed stages
+        if (e == hipSuccess) e = dpd::launch_fold(b->lp, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
         for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+            if (s == 2 && !b->lp.any_virial) continue;   // no virial kernel: nothing timed
+            if (s == 3 && b->lp.fuse) continue;          // integrated inside the force kernel
             float ms = 0.0f;
             e = hipEventElapsedTime(&ms, ev[s], ev[s + 1]);
             acc[s] += ms;
@@ -815,6 +1073,35 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
     b->keys_valid = true;
     b->have_force = true;
     for (int s = 0; s < 4; ++s) ms_out[s] = acc[s] / (double)nsteps;
+    return DPD_OK;
+}
+
+int dpd_time_force(dpd_box b, int32_t reps, double* ms_out)
+{
+    if (!b || !ms_out) return fail(DPD_EINVAL, "dpd_time_force: null argument");
+    if (reps < 1 || reps > 10000) return fail(DPD_EINVAL, "dpd_time_force: reps must be in 1..10000");
+    if (!ready(b)) return fail(DPD_ESTATE, "dpd_time_force: set params, seed and state first");
+    // forces of the current positions; the state does not advance
+    if (!b->binned) {
+        HIPCHK(dpd::launch_bin(b->lp, b->stream));
+        b->binned = true;
+        b->keys_valid = false;
+    }
+    b->have_force = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream, false);          // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream, false);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_time_force: %s", hipGetErrorString(e));
+    *ms_out = (double)ms / reps;
     return DPD_OK;
 }
 
@@ -831,6 +1118,24 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         HIPCHK(dpd::launch_bin(b->lp, b->stream));
         b->binned = true;
         b->keys_valid = false;
+    }
+    std::string key;
+    if (tune_cache_on()) {
+        key = tune_key_prefix(b->stream) + "box|" + box_tune_part(b);
+        TuneEntry e;
+        if (tune_lookup(key, &e) && (e.threads == 256 || e.threads == 512 || e.threads == 1024) &&
+            e.tile[0] >= 1 && e.tile[1] >= 1 && e.tile[2] >= 1 && e.tile[0] <= 16 && e.tile[1] <= 16 &&
+            e.tile[2] <= 16 && (size_t)tile_for(b, e.tile, e.threads).lds_bytes <= kLdsLimit) {
+            for (int k = 0; k < 3; ++k) b->tile_req[k] = e.tile[k];
+            b->threads_req = e.threads;
+            b->have_force = false;
+            b->graph_dirty = true;
+            const int rc = push_desc(b);
+            if (rc) return rc;
+            for (int k = 0; k < 3; ++k) tile_out[k] = b->hd.tc.T[k];
+            if (ms_out) *ms_out = e.ms;
+            return DPD_OK;
+        }
     }
     const auto& cand = kTuneCand;
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
@@ -850,9 +1155,9 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         rc = push_desc(b);
         if (rc) break;
         float ms = 0.0f;
-        hipError_t e = dpd::launch_force(b->lp, b->stream);          // warm-up
+        hipError_t e = dpd::launch_force(b->lp, b->stream, false);          // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream, false);
         if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -877,6 +1182,7 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     const int rc2 = push_desc(b);
     if (rc) return rc;
     if (rc2) return rc2;
+    if (won && !key.empty()) tune_store(key, bt, bthreads, best);
     for (int k = 0; k < 3; ++k) tile_out[k] = bt[k];
     if (ms_out) *ms_out = best;
     return DPD_OK;
@@ -985,8 +1291,7 @@ int dpd_destroy(dpd_box b)
 {
     if (!b) return DPD_OK;
     hipError_t e = hipStreamSynchronize(b->stream);
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    b->graphs.release();
     delete b;
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_destroy: %s", hipGetErrorString(e));
     return DPD_OK;
@@ -1022,13 +1327,13 @@ int batch_refresh(dpd_batch_s* bt)
         if (h[i].tc.threads != threads) h[i].tc = tile_for(bt->boxes[i], bt->boxes[i]->tile_req, threads);
         lds = std::max(lds, h[i].tc.lds_bytes);
         virial |= (h[i].flags & DPD_FLAG_VIRIAL) != 0;
-        species |= h[i].fc.ntypes > 1;
+        species |= bt->boxes[i]->lp.species;
         walls |= bt->boxes[i]->lp.walls;
         for (int k = 0; k < dpd::kNumWork; ++k)
             bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
     }
     bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species ||
-                   bt->lp.walls != walls || bt->lp.force_threads != threads;
+                   bt->lp.walls != walls || bt->lp.force_threads != threads || bt->lp.fuse != !walls;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
         changed |= bt->lp.total[k] != tot;
@@ -1043,7 +1348,8 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.walls = walls;
     bt->lp.force_threads = threads;
     bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
-    if (changed) bt->graph_steps = 0;   // launch shape changed: capture again
+    bt->lp.fuse = !walls;
+    if (changed) bt->graph_dirty = true;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));
     HIPCHK(hipMemcpyAsync(bt->d_desc, h.data(), (size_t)nb * sizeof(dpd::BoxDesc), hipMemcpyHostToDevice, bt->stream));
     HIPCHK(hipMemcpyAsync(bt->d_pre, bt->pre.data(), bt->pre.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream));
@@ -1116,6 +1422,37 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
         saved.push_back({b->tile_req[0], b->tile_req[1], b->tile_req[2]});
         saved_threads.push_back(b->threads_req);
     }
+    std::string key;
+    if (tune_cache_on()) {
+        key = tune_key_prefix(bt->stream) + "batch";
+        for (size_t i = 0; i < bt->boxes.size(); ++i) {
+            const dpd_box_s* b = bt->boxes[i];
+            char own[48];
+            std::snprintf(own, sizeof own, "/t%dx%dx%d@%d", b->tile_req[0], b->tile_req[1], b->tile_req[2],
+                          b->threads_req);
+            key += "|" + box_tune_part(b) + own;
+        }
+        TuneEntry e;
+        bool usable = tune_lookup(key, &e) && (e.threads == 256 || e.threads == 512 || e.threads == 1024);
+        const bool uniform = usable && e.tile[0] > 0;
+        for (size_t i = 0; i < bt->boxes.size() && usable; ++i) {
+            const int* t = uniform ? e.tile : saved[i].data();
+            usable = (size_t)tile_for(bt->boxes[i], t, e.threads).lds_bytes <= kLdsLimit;
+        }
+        if (usable) {
+            for (size_t i = 0; i < bt->boxes.size() && rc == DPD_OK; ++i) {
+                dpd_box_s* b = bt->boxes[i];
+                for (int k = 0; k < 3; ++k) b->tile_req[k] = uniform ? e.tile[k] : saved[i][k];
+                b->threads_req = e.threads;
+                rc = push_desc(b);
+            }
+            if (rc == DPD_OK) rc = batch_refresh(bt);
+            if (rc) return rc;
+            for (int k = 0; k < 3; ++k) tile_out[k] = uniform ? e.tile[k] : 0;
+            if (ms_out) *ms_out = e.ms;
+            return DPD_OK;
+        }
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1142,9 +1479,9 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
         if (rc == DPD_OK) rc = batch_refresh(bt);
         if (rc) break;
         float ms = 0.0f;
-        hipError_t e = dpd::launch_force(bt->lp, bt->stream);     // warm-up
+        hipError_t e = dpd::launch_force(bt->lp, bt->stream, false);     // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, bt->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(bt->lp, bt->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(bt->lp, bt->stream, false);
         if (e == hipSuccess) e = hipEventRecord(e1, bt->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1175,8 +1512,19 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
     if (rc2 == DPD_OK) rc2 = batch_refresh(bt);
     if (rc) return rc;
     if (rc2) return rc2;
+    if (have_best && !key.empty()) tune_store(key, bt3, bthreads, best);
     for (int k = 0; k < 3; ++k) tile_out[k] = bt3[k];
     if (ms_out) *ms_out = best;
+    return DPD_OK;
+}
+
+int dpd_set_tune_cache(const char* path)
+{
+    TuneCacheFile& f = tune_file();
+    std::lock_guard<std::mutex> lk(f.mu);
+    f.path = path ? path : "";
+    f.entries.clear();
+    if (!f.path.empty()) tune_read(f);
     return DPD_OK;
 }
 
@@ -1200,23 +1548,24 @@ int dpd_batch_step(dpd_batch bt, int64_t nsteps)
     // One graph holds the whole run (up to kBatchGraphMax steps), so a run is
     // a single launch; longer runs replay it.  Short runs (a serving quantum
     // on a changing set of boxes) are launched directly.
-    int64_t left = nsteps;
+    const int64_t left = nsteps - (nbinned ? 1 : 0);
+    const bool graphs = nsteps >= kBatchGraphMin;
+    const RunPlan rp = graphs ? plan_run(left, kBatchGraphMax) : RunPlan{};
+    hipGraphExec_t gfull = nullptr, gtail = nullptr;
+    if (rp.full && (rc = graph_for(bt->graphs, bt->graph_dirty, bt->lp, rp.g, &gfull))) return rc;
+    if (rp.tail && (rc = graph_for(bt->graphs, bt->graph_dirty, bt->lp, rp.tail, &gtail))) return rc;
     if (nbinned) {                       // first step reuses the cell lists
         HIPCHK(enqueue_step_tail(bt->lp, bt->stream));
         for (dpd_box_s* b : bt->boxes) b->binned = false;
-        --left;
     }
-    if (nsteps >= kBatchGraphMin) {
-        const int64_t g = nsteps < kBatchGraphMax ? nsteps : kBatchGraphMax;
-        if (bt->graph_steps != g) {
-            rc = capture(bt->lp, g, &bt->cap_stream, &bt->graph);
-            if (rc) return rc;
-            bt->graph_steps = g;
-        }
-        for (; left >= g; left -= g) HIPCHK(hipGraphLaunch(bt->graph, bt->stream));
+    if (graphs) {
+        for (int64_t k = 0; k < rp.full; ++k) HIPCHK(hipGraphLaunch(gfull, bt->stream));
+        if (rp.tail) HIPCHK(hipGraphLaunch(gtail, bt->stream));
+        if (left == 0) HIPCHK(dpd::launch_fold(bt->lp, bt->stream));
+    } else {
+        HIPCHK(enqueue_steps(bt->lp, left, bt->stream));
+        HIPCHK(dpd::launch_fold(bt->lp, bt->stream));   // the last step's reductions
     }
-    HIPCHK(enqueue_steps(bt->lp, left, bt->stream));
-    HIPCHK(dpd::launch_fold(bt->lp, bt->stream));  // the last step's reductions
     // later work on each box's own stream waits for the batch
     HIPCHK(hipEventRecord(bt->done, bt->stream));
     for (dpd_box_s* b : bt->boxes) {
@@ -1232,8 +1581,7 @@ int dpd_batch_destroy(dpd_batch bt)
 {
     if (!bt) return DPD_OK;
     hipError_t e = hipStreamSynchronize(bt->stream);
-    if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
-    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+    bt->graphs.release();
     if (bt->done) (void)hipEventDestroy(bt->done);
     delete bt;
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_batch_destroy: %s", hipGetErrorString(e));

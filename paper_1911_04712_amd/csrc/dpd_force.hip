@@ -226,8 +226,112 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
     }
 }
 
-template <bool kSp, int kThreads>
-__global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restrict__ desc,
+constexpr int kProfSlots = 64;  // flow-profile slabs one tile sums in LDS before its global atomics
+
+// Write-out of tile t: each tile particle's total force, once, in cell
+// order.  With kFuse the particle's kick-drift follows at once (Sec. 3.1,
+// time-stepping step 5, done here because the force is final): the next
+// position and velocity go to pos_a / vel_a, its next cell and arrival slot
+// to keyslot and the cell counters, and the tile's FP64 sums (fixed order:
+// lanes, then waves) to its own entry of `partials`, which the fold adds
+// up in tile order.  src(rw, k, x, v, f) gives particle k of tile row rw:
+// its position x^n, stored velocity (w = species) and force.  scr is LDS
+// the kernel no longer uses (at least kProfSlots * 12 + waves * 40 bytes).
+// Every thread of the workgroup calls it.
+template <bool kFuse, int kThreads, typename Src>
+__device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* rows, int nrows, int o_grad,
+                                           unsigned char* scr, Src src)
+{
+    constexpr int nw = kThreads >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    long long* p_sum = (long long*)scr;
+    int* p_cnt = (int*)(scr + kProfSlots * 8);
+    double* s_red = (double*)(scr + kProfSlots * 12);
+    const StepConst& sc = d.sc;
+    const int nbins = kFuse ? sc.nbins : 0;
+    const int blo = nbins > 0 ? max(0, min((int)((float)o_grad * sc.grad_scale), nbins - 1)) : 0;
+    if constexpr (kFuse) {
+        for (int k = tid; k < kProfSlots; k += kThreads) {
+            p_sum[k] = 0;
+            p_cnt[k] = 0;
+        }
+        __syncthreads();
+    }
+    double m[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool bad = false, esc = false;
+    for (int r = wave; r < nrows; r += nw) {
+        const int4 rw = rows[r];
+        for (int k0 = 0; k0 < rw.y; k0 += 64) {            // wave-uniform: every lane reaches the atomics
+            const int k = k0 + lane;
+            const bool live = k < rw.y;
+            const int g = rw.z + k;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
+            if (live) {
+                src(rw, k, x, v, f);
+                d.force[g] = f;
+            }
+            if constexpr (kFuse) {
+                const Kicked kk = kick_drift(x, v, f, sc);
+                bad |= !kk.fin;
+                esc |= kk.esc;
+                const int c = live ? cell_of(kk.nx, kk.ny, kk.nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
+                const ArrivalTicket tk = arrival_issue(c, live, d.count);   // atomic in flight meanwhile
+                chunk_add(c, live, d.bsum);
+                if (live) {
+                    d.pos_a[g] = make_float4(kk.nx, kk.ny, kk.nz, x.w);
+                    d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, v.w);
+                }
+                if (live && kk.fin) {
+                    add_partials(m, kk);
+                    if (nbins > 0) {
+                        const int b = profile_bin(x, sc);
+                        const long long q = profile_units(kk.vcx, kk.vcy, kk.vcz, sc);
+                        const int sl = b - blo;
+                        if (sl >= 0 && sl < kProfSlots) {
+                            atomicAdd((unsigned long long*)&p_sum[sl], (unsigned long long)q);
+                            atomicAdd(&p_cnt[sl], 1);
+                        } else {
+                            atomicAdd((unsigned long long*)&d.profile[2 * b], (unsigned long long)q);
+                            atomicAdd((unsigned long long*)&d.profile[2 * b + 1], 1ull);
+                        }
+                    }
+                }
+                const int slot = arrival_finish(tk, live);
+                if (live) d.keyslot[g] = make_int2(c, slot);
+            }
+        }
+    }
+    if constexpr (kFuse) {
+        if (bad) atomicOr(&d.st->nonfinite, 1);
+        if (esc) atomicOr(&d.st->escaped, 1);
+#pragma unroll
+        for (int k = 0; k < kPartials; ++k) {
+            const double w = wave_sum(m[k]);
+            if (lane == 0) s_red[wave * kPartials + k] = w;
+        }
+        __syncthreads();
+        if (tid < kPartials) {
+            double sum = 0.0;
+            for (int w = 0; w < nw; ++w) sum += s_red[w * kPartials + tid];
+            d.partials[(size_t)t * kPartials + tid] = sum;
+        }
+        if (nbins > 0)
+            for (int k = tid; k < kProfSlots; k += kThreads)
+                if (p_cnt[k]) {
+                    atomicAdd((unsigned long long*)&d.profile[2 * (blo + k)], (unsigned long long)p_sum[k]);
+                    atomicAdd((unsigned long long*)&d.profile[2 * (blo + k) + 1], (unsigned long long)p_cnt[k]);
+                }
+        if (t == 0 && tid == 0) {      // the fold adds up one partial per tile
+            d.st->fold_count = (unsigned)d.tc.ntiles;
+            d.st->fold_pending = 1;
+        }
+    }
+}
+
+// 1024-thread workgroups: at most 64 VGPRs, so that two fit a CU (8 waves
+// per SIMD); the smaller ones fit their LDS-bound count of workgroups anyway
+template <bool kSp, int kThreads, bool kFuse>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThreads == 1024 ? 8 : 1))) void k_force_tiled(const BoxDesc* __restrict__ desc,
                                                              const int* __restrict__ pre, int nbox)
 {
     const int* __restrict__ pre_ = pre + kWTile * (nbox + 1);
@@ -240,6 +344,11 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     const int* __restrict__ cell_start = d.cell_start;
     float4* __restrict__ force = d.force;
     int* __restrict__ nonfinite = &d.st->nonfinite;
+    // constants the loops use, read once: after an LDS or global atomic the
+    // compiler would otherwise fetch them from the descriptor again
+    const PairConst pc = fc.pc;
+    const float Lf0 = fc.L[0], Lf1 = fc.L[1], Lf2 = fc.L[2];
+    const int ux = tc.ux;
     extern __shared__ __align__(16) unsigned char lds[];
     float4* sp = (float4*)lds;                                  // staged positions (image-shifted), w = id
     float4* sv = (float4*)(lds + tc.off_sv);                    // staged velocities, w = tile index or -1 (+ species)
@@ -312,6 +421,9 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     __syncthreads();
     const int nt = s_scr[0];
 
+    const int o_grad = fc.grad_axis == 0 ? o0 : (fc.grad_axis == 1 ? o1 : o2);   // tile origin along the profile axis
+    unsigned char* scr = lds + tc.off_q;                // the queues' LDS, free again at write-out
+
     if (S > tc.smax || nt > tc.pmax || (d.flags & kFlagReference)) {
         // Overfull tile (or the box asks for the reference path): gather
         // from HBM, same arithmetic and same bits.
@@ -322,6 +434,16 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
                 force[rw.z + k] = gather_force_one<kSp>(rw.z + k, pos, vel, cell_start, fc, step, bad);
         }
         if (bad) atomicOr(nonfinite, 1);
+        // the write-out visits the particles with the same lanes, so each
+        // lane reads back the force it wrote
+        if constexpr (kFuse)
+            write_tile<kFuse, kThreads>(d, t, rows, nrows, o_grad, scr,
+                                        [&](const int4& rw, int k, float4& x, float4& v, float4& f) {
+                                            const int g = rw.z + k;
+                                            x = pos[g];
+                                            v = vel[g];
+                                            f = force[g];
+                                        });
         return;
     }
 
@@ -335,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
         const int nsrows = S1 * S2;
         int top = 1;
         while (top * 2 <= nsrows) top *= 2;
-        const float shx_lo = o0 == 0 ? -fc.L[0] : 0.0f, shx_hi = o0 + P0 == L0 ? fc.L[0] : 0.0f;
+        const float shx_lo = o0 == 0 ? -Lf0 : 0.0f, shx_hi = o0 + P0 == L0 ? Lf0 : 0.0f;
         for (int s0 = tid; s0 < S; s0 += 2 * kThreads) {
             int src[2], tiv[2];
             float shx[2], shy[2], shz[2];
@@ -353,8 +475,8 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
                 src[u] = cg[cs] + (s - cst[cs]);
                 shx[u] = seg == 0 ? shx_lo : (seg == 2 ? shx_hi : 0.0f);
                 const int gy = o1 - 1 + ly, gz = o2 - 1 + lz;
-                shy[u] = gy < 0 ? -fc.L[1] : (gy >= L1 ? fc.L[1] : 0.0f);
-                shz[u] = gz < 0 ? -fc.L[2] : (gz >= L2 ? fc.L[2] : 0.0f);
+                shy[u] = gy < 0 ? -Lf1 : (gy >= L1 ? Lf1 : 0.0f);
+                shz[u] = gz < 0 ? -Lf2 : (gz >= L2 ? Lf2 : 0.0f);
                 const bool tile_row = ly >= 1 && ly <= P1 && lz >= 1 && lz <= P2;
                 tiv[u] = (tile_row && seg == 1) ? rows[(ly - 1) + P1 * (lz - 1)].w + (s - b1) : -1;
             }
@@ -408,7 +530,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     const int roff = rsgn * S0 * (fdy + S1 * fdz);      // staged-cell offset of the slot's row
     int rs_ = 0, rl_ = 0;
     // home units (ux consecutive cells of a tile row) go to the waves in turn
-    const int upr = (P0 + tc.ux - 1) / tc.ux;           // units per tile row
+    const int upr = (P0 + ux - 1) / ux;                 // units per tile row
     const int nunits = upr * nrows;
     // each wave takes the next unit when it is done with one (face rows
     // cost about twice an interior row, so a fixed deal of units to waves
@@ -422,8 +544,8 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
     for (int un = wave; un < nunits; un = next_unit()) {
         const int row = small_div(un, inv_upr);         // row (y, z) of the unit, y fastest
         const int rz = small_div(row, inv_p1), ry = row - rz * P1;
-        const int lx = 1 + (un - row * upr) * tc.ux, ly = ry + 1, lz = rz + 1;
-        const int w = min(tc.ux, P0 + 1 - lx);          // cells in this unit
+        const int lx = 1 + (un - row * upr) * ux, ly = ry + 1, lz = rz + 1;
+        const int w = min(ux, P0 + 1 - lx);             // cells in this unit
         const int cown = lx + S0 * (ly + S1 * lz);
         const int own_s = __builtin_amdgcn_readfirstlane(cst[cown]);
         const int own_e = __builtin_amdgcn_readfirstlane(cst[cown + w]);
@@ -475,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
                     __builtin_amdgcn_wave_barrier();
                     int fh = 0;
                     do {
-                        flush_hit<kSp>(q[fh + lane], sp, sv, acc, step, fc.pc, tab, bad);
+                        flush_hit<kSp>(q[fh + lane], sp, sv, acc, step, pc, tab, bad);
                         fh += 64;
                     } while (qt - fh >= 64);
                     const unsigned rest = q[fh + lane];          // move what is left (< 64) to the front
@@ -542,18 +664,24 @@ __global__ __launch_bounds__(kThreads) void k_force_tiled(const BoxDesc* __restr
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < qt) flush_hit<kSp>(q[lane], sp, sv, acc, step, fc.pc, tab, bad);
+    if (lane < qt) flush_hit<kSp>(q[lane], sp, sv, acc, step, pc, tab, bad);
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
 
-    // 5. each tile particle's force is written once, in cell order
-    for (int r = wave; r < nrows; r += nw) {
-        const int4 rw = rows[r];
-        for (int k = lane; k < rw.y; k += 64) {
-            const int ti = rw.w + k;
-            force[rw.z + k] = finish_force(acc[3 * ti], acc[3 * ti + 1], acc[3 * ti + 2], sp[rw.x + k], fc);
-        }
-    }
+    // 5. each tile particle's force is written once, in cell order (a tile
+    //    particle is staged without an image shift, so sp holds x^n); with
+    //    kFuse its kick-drift follows
+    write_tile<kFuse, kThreads>(d, t, rows, nrows, o_grad, scr,
+                                [&](const int4& rw, int k, float4& x, float4& v, float4& f) {
+                                    const int ti = rw.w + k;
+                                    x = sp[rw.x + k];
+                                    v = sv[rw.x + k];
+                                    // the staged .w holds the tile index (and the species in
+                                    // its top 8 bits with kSp); a launch without kSp has only
+                                    // species-0 particles
+                                    v.w = __int_as_float(kSp ? (int)((unsigned)__float_as_int(v.w) >> 24) : 0);
+                                    f = finish_force(acc[3 * ti], acc[3 * ti + 1], acc[3 * ti + 2], x, fc);
+                                });
 }
 
 TileConst make_tile_const(const int* cells, double rho, const int* tile, int threads, int smax_override,
@@ -593,33 +721,37 @@ TileConst make_tile_const(const int* cells, double rho, const int* tile, int thr
     return tc;
 }
 
-template <bool kSp>
+template <bool kSp, bool kFuse>
 static void launch_tiled(const LaunchPlan& lp, hipStream_t s)
 {
     const dim3 grid(lp.total[kWTile]);
     switch (lp.force_threads) {
     case 256:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 256>), grid, dim3(256), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        hipLaunchKernelGGL((k_force_tiled<kSp, 256, kFuse>), grid, dim3(256), lp.lds_force, s, lp.desc, lp.pre,
+                           lp.nbox);
         break;
     case 1024:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 1024>), grid, dim3(1024), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        hipLaunchKernelGGL((k_force_tiled<kSp, 1024, kFuse>), grid, dim3(1024), lp.lds_force, s, lp.desc, lp.pre,
+                           lp.nbox);
         break;
     default:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 512>), grid, dim3(512), lp.lds_force, s, lp.desc, lp.pre, lp.nbox);
+        hipLaunchKernelGGL((k_force_tiled<kSp, 512, kFuse>), grid, dim3(512), lp.lds_force, s, lp.desc, lp.pre,
+                           lp.nbox);
         break;
     }
 }
 
-hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate)
 {
     if (lp.reference_force) {
         if (lp.total[kWPart] > 0)
             hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
+        const bool fuse = integrate && lp.fuse;
         if (lp.species)
-            launch_tiled<true>(lp, s);
+            fuse ? launch_tiled<true, true>(lp, s) : launch_tiled<true, false>(lp, s);
         else
-            launch_tiled<false>(lp, s);
+            fuse ? launch_tiled<false, true>(lp, s) : launch_tiled<false, false>(lp, s);
     }
     return hipGetLastError();
 }
@@ -627,9 +759,13 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s)
 hipError_t force_tiled_prepare(int lds_bytes)
 {
     if (lds_bytes <= 65536) return hipSuccess;
-    const void* fns[] = {(const void*)k_force_tiled<false, 256>, (const void*)k_force_tiled<false, 512>,
-                         (const void*)k_force_tiled<false, 1024>, (const void*)k_force_tiled<true, 256>,
-                         (const void*)k_force_tiled<true, 512>, (const void*)k_force_tiled<true, 1024>};
+    const void* fns[] = {
+        (const void*)k_force_tiled<false, 256, false>, (const void*)k_force_tiled<false, 512, false>,
+        (const void*)k_force_tiled<false, 1024, false>, (const void*)k_force_tiled<true, 256, false>,
+        (const void*)k_force_tiled<true, 512, false>, (const void*)k_force_tiled<true, 1024, false>,
+        (const void*)k_force_tiled<false, 256, true>, (const void*)k_force_tiled<false, 512, true>,
+        (const void*)k_force_tiled<false, 1024, true>, (const void*)k_force_tiled<true, 256, true>,
+        (const void*)k_force_tiled<true, 512, true>, (const void*)k_force_tiled<true, 1024, true>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return e;

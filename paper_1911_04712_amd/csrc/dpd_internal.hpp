@@ -34,7 +34,7 @@ struct DevStats {
     unsigned int fold_pending;      // integrate partials not yet folded into the reductions
     int nonfinite;
     int escaped;
-    int pad0;
+    unsigned int fold_count;        // partials the pending fold adds up (integrate blocks or force tiles)
     double last[kPartials];         // reductions of the last step
     double sum_kT_centred;
     double sum_pressure;
@@ -156,7 +156,7 @@ struct BoxDesc {
     int* count;                // particles per cell (zeroed by the scan)
     int* cell_start;           // nc + 1
     int* bsum;                 // particles per kSubChunk cells (zeroed by the scatter)
-    double* partials;          // integrate per-block partials (kPartials each)
+    double* partials;          // FP64 partials of the last step (kPartials per integrate block or force tile)
     long long* profile;        // flow profile accumulators (sum, count) per slab
     DevStats* st;
     int n, nc, nchunks, nsub;
@@ -184,6 +184,8 @@ struct LaunchPlan {
     bool walls;                // some box has walls or frozen particles: the wall integrate kernel
     bool any_virial;
     bool reference_force;      // single box flagged DPD_FLAG_REFERENCE_FORCE
+    bool fuse;                 // the tile kernel integrates each particle once its force is final
+                               // (no walls and no frozen particles in the launch, tile kernel)
 };
 
 // Layout of a box inside its caller-provided workspace.  All offsets are
@@ -198,7 +200,7 @@ struct Layout {
     size_t count;             // int[nc]    particles per cell
     size_t cell_start;        // int[nc+1]
     size_t bsum;              // int[nsub]
-    size_t partials;          // double[kIntegrateMaxBlocks * kPartials]
+    size_t partials;          // double[max(kIntegrateMaxBlocks, nc) * kPartials]: per block or per tile
     size_t profile;           // long long[kProfileMaxBins * 2] (sum, count)
     size_t stats;             // DevStats
     size_t flags;             // int[4] scratch flags
@@ -229,7 +231,9 @@ hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsign
 hipError_t launch_get_frozen(const float4* pos, const float4* vel, int n, unsigned char* frozen_by_id, hipStream_t s);
 hipError_t launch_wall_sdf(const float4* pos, int n, const StepConst& sc, float* sdf_by_id, hipStream_t s);
 hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
-hipError_t launch_force(const LaunchPlan& lp, hipStream_t s);
+// integrate: a step's force launch, which also integrates when lp.fuse (the
+// tuners and timers pass false: forces only, the state is left alone)
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate);
 hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
 hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s);
@@ -242,6 +246,145 @@ hipError_t launch_to_rows(const float4* src, const float4* sub, float sub_scale,
                           float* out3, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr4, const uint32_t* key2, int64_t n, uint32_t* out4, hipStream_t s);
 hipError_t launch_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi, hipStream_t s);
+
+// Arrival slot in a per-cell counter, aggregated over runs of equal keys in
+// a wave: lanes l0..l1 holding the same key (consecutive lanes) take one
+// atomicAdd of the run length and slots base + (l - l0).  Particles in cell
+// order mostly stay in their cell, so runs are about rho long.  Lanes with
+// valid == false must pass key = -1.  All lanes of the wave must call both
+// halves (arrival_issue, then arrival_finish).
+struct ArrivalTicket {
+    int base;       // counter value taken by the run head (head lanes)
+    int my_head;    // lane of this lane's run head
+};
+
+// First half: issue the run heads' atomics.  The returned
+// value is not needed until arrival_finish, so other work can hide the
+// atomic's round trip.
+__device__ __forceinline__ ArrivalTicket arrival_issue(int key, bool valid, int* __restrict__ count)
+{
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = valid && (lane == 0 || prev != key);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long live = __ballot(valid);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    ArrivalTicket t;
+    t.my_head = 63 - __clzll(heads & upto);                         // valid lanes only
+    int run_end = 64;
+    const unsigned long long after = heads & ~upto;
+    if (after) run_end = __ffsll((long long)after) - 1;
+    const int nlive = __popcll(live);                               // valid lanes are a prefix
+    if (run_end > nlive) run_end = nlive;
+    t.base = 0;
+    if (head) t.base = atomicAdd(&count[key], run_end - lane);
+    return t;
+}
+
+// Particle counts per sub-chunk of kSubChunk cells, one device atomic per
+// run of equal sub-chunks in a wave.  Same-address device atomics
+// serialise, so the counters are kept small enough that only a few waves
+// (about kSubChunk rho / 64) add to each.  Same contract as arrival_issue;
+// nothing is returned.
+__device__ __forceinline__ void chunk_add(int key, bool valid, int* __restrict__ bsum)
+{
+    const int lane = threadIdx.x & 63;
+    const int ck = valid ? key / kSubChunk : -1;
+    const int prev = __shfl_up(ck, 1, 64);
+    const bool head = valid && (lane == 0 || prev != ck);
+    const unsigned long long heads = __ballot(head);
+    const int nlive = __popcll(__ballot(valid));                    // valid lanes are a prefix
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const unsigned long long after = heads & ~upto;
+    int run_end = after ? __ffsll((long long)after) - 1 : 64;
+    if (run_end > nlive) run_end = nlive;
+    if (head) atomicAdd(&bsum[ck], run_end - lane);
+}
+
+// Second half: every lane of the wave must call it.
+__device__ __forceinline__ int arrival_finish(const ArrivalTicket& t, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    const int base = __shfl(t.base, valid ? t.my_head : lane, 64);
+    return base + (lane - t.my_head);
+}
+
+// Kick and drift of one free particle of a box without walls (Sec. 3.1,
+// time-stepping step 5: v^{n+1/2} = v^{n-1/2} + dt f^n / m, then
+// x^{n+1} = x^n + dt v^{n+1/2}), the position rounded to the grid q and
+// wrapped into [0, L).  Shared by the integrate kernel and the force kernel's
+// fused epilogue, so both compute the same bits.  A non-finite result keeps
+// the old position (fin = false); esc reports a move of a cell or more, or a
+// position that still fell outside the box (clamped inside).
+struct Kicked {
+    float nx, ny, nz;      // x^{n+1}
+    float vx, vy, vz;      // v^{n+1/2}
+    float vcx, vcy, vcz;   // v^{n-1/2} + dt f^n / (2 m): the time-centred velocity
+    bool fin, esc;
+};
+
+__device__ __forceinline__ Kicked kick_drift(float4 x, float4 v, float4 f, const StepConst& sc)
+{
+    Kicked k;
+    k.vcx = fmaf(f.x, sc.half_dtm, v.x);
+    k.vcy = fmaf(f.y, sc.half_dtm, v.y);
+    k.vcz = fmaf(f.z, sc.half_dtm, v.z);
+    k.vx = fmaf(f.x, sc.dtm, v.x);
+    k.vy = fmaf(f.y, sc.dtm, v.y);
+    k.vz = fmaf(f.z, sc.dtm, v.z);
+    float nx = fmaf(k.vx, sc.dt, x.x), ny = fmaf(k.vy, sc.dt, x.y), nz = fmaf(k.vz, sc.dt, x.z);
+    k.fin = isfinite(k.vx) && isfinite(k.vy) && isfinite(k.vz) && isfinite(nx) && isfinite(ny) && isfinite(nz);
+    if (!k.fin) {
+        nx = x.x;
+        ny = x.y;
+        nz = x.z;
+    }
+    k.esc = fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
+    nx = rintf(nx * sc.inv_q) * sc.q;
+    ny = rintf(ny * sc.inv_q) * sc.q;
+    nz = rintf(nz * sc.inv_q) * sc.q;
+    if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
+    if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
+    if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
+    if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
+        k.esc = true;
+        nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
+        ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
+        nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
+    }
+    k.nx = nx;
+    k.ny = ny;
+    k.nz = nz;
+    return k;
+}
+
+// FP64 sums of one moved particle into m[kPartials]: momentum and kinetic
+// energy of v^{n+1/2}, kinetic energy of the time-centred velocity.
+__device__ __forceinline__ void add_partials(double* m, const Kicked& k)
+{
+    m[0] += (double)k.vx;
+    m[1] += (double)k.vy;
+    m[2] += (double)k.vz;
+    m[3] += (double)k.vx * k.vx + (double)k.vy * k.vy + (double)k.vz * k.vz;
+    m[4] += (double)k.vcx * k.vcx + (double)k.vcy * k.vcy + (double)k.vcz * k.vcz;
+}
+
+// Flow-profile slab of a particle at x^n (grad_axis coordinate) and its
+// fixed-point time-centred flow velocity.
+__device__ __forceinline__ int profile_bin(float4 x, const StepConst& sc)
+{
+    const float g = sc.grad_axis == 0 ? x.x : (sc.grad_axis == 1 ? x.y : x.z);
+    int b = (int)(g * sc.grad_scale);
+    return b < 0 ? 0 : (b > sc.nbins - 1 ? sc.nbins - 1 : b);
+}
+
+// (the components come as separate values: a runtime pick from a struct
+// would be compiled as an indexed load from a stack copy of it)
+__device__ __forceinline__ long long profile_units(float vcx, float vcy, float vcz, const StepConst& sc)
+{
+    const float vflow = sc.flow_axis == 0 ? vcx : (sc.flow_axis == 1 ? vcy : vcz);
+    return llrint((double)vflow * kProfScale);
+}
 
 // Box of workgroup `b` of a launch group (exclusive prefix pre[0..nbox]).
 __device__ __forceinline__ int find_box(const int* __restrict__ pre, int nbox, int b)

@@ -18,68 +18,6 @@
 
 namespace dpd {
 
-// Arrival slot in a per-cell counter, aggregated over runs of equal keys in
-// a wave: lanes l0..l1 holding the same key (consecutive lanes) take one
-// atomicAdd of the run length and slots base + (l - l0).  Particles in cell
-// order mostly stay in their cell, so runs are about rho long.  Lanes with
-// valid == false must pass key = -1.  All lanes of the wave must call both
-// halves (arrival_issue, then arrival_finish).
-struct ArrivalTicket {
-    int base;       // counter value taken by the run head (head lanes)
-    int my_head;    // lane of this lane's run head
-};
-
-// First half: issue the run heads' atomics.  The returned
-// value is not needed until arrival_finish, so other work can hide the
-// atomic's round trip.
-__device__ __forceinline__ ArrivalTicket arrival_issue(int key, bool valid, int* __restrict__ count)
-{
-    const int lane = threadIdx.x & 63;
-    const int prev = __shfl_up(key, 1, 64);
-    const bool head = valid && (lane == 0 || prev != key);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long live = __ballot(valid);
-    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    ArrivalTicket t;
-    t.my_head = 63 - __clzll(heads & upto);                         // valid lanes only
-    int run_end = 64;
-    const unsigned long long after = heads & ~upto;
-    if (after) run_end = __ffsll((long long)after) - 1;
-    const int nlive = __popcll(live);                               // valid lanes are a prefix
-    if (run_end > nlive) run_end = nlive;
-    t.base = 0;
-    if (head) t.base = atomicAdd(&count[key], run_end - lane);
-    return t;
-}
-
-// Particle counts per sub-chunk of kSubChunk cells, one device atomic per
-// run of equal sub-chunks in a wave.  Same-address device atomics
-// serialise, so the counters are kept small enough that only a few waves
-// (about kSubChunk rho / 64) add to each.  Same contract as arrival_issue;
-// nothing is returned.
-__device__ __forceinline__ void chunk_add(int key, bool valid, int* __restrict__ bsum)
-{
-    const int lane = threadIdx.x & 63;
-    const int ck = valid ? key / kSubChunk : -1;
-    const int prev = __shfl_up(ck, 1, 64);
-    const bool head = valid && (lane == 0 || prev != ck);
-    const unsigned long long heads = __ballot(head);
-    const int nlive = __popcll(__ballot(valid));                    // valid lanes are a prefix
-    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const unsigned long long after = heads & ~upto;
-    int run_end = after ? __ffsll((long long)after) - 1 : 64;
-    if (run_end > nlive) run_end = nlive;
-    if (head) atomicAdd(&bsum[ck], run_end - lane);
-}
-
-// Second half: every lane of the wave must call it.
-__device__ __forceinline__ int arrival_finish(const ArrivalTicket& t, bool valid)
-{
-    const int lane = threadIdx.x & 63;
-    const int base = __shfl(t.base, valid ? t.my_head : lane, 64);
-    return base + (lane - t.my_head);
-}
-
 // ---------------------------------------------------------------------------
 // utility kernels
 // ---------------------------------------------------------------------------
@@ -606,91 +544,92 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
             f = force[i];
         }
         const bool frozen = kWalls && (__float_as_int(v.w) & kFrozenBit) != 0;   // wall particles never move
-        const float vcx = fmaf(f.x, sc.half_dtm, v.x), vcy = fmaf(f.y, sc.half_dtm, v.y),
-                    vcz = fmaf(f.z, sc.half_dtm, v.z);
-        float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
-        if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
-        float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
-              nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
-        bool turned = false;
-        if (kWalls && frozen && sc.wall_kind == 3) {
-            // a turning cylinder turns its frozen layer rigidly by omega dt
-            // about the axis (the particle takes the wall velocity at its
-            // new, grid-rounded position below)
-            float c1, c2;
-            const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
-            if (sc.omega[cyl] != 0.0f) {
-                const float cs = sc.rot[cyl][0], sn = sc.rot[cyl][1];
-                const float3 d = from_axes(sc, fmaf(cs, c1, -sn * c2) - c1, fmaf(sn, c1, cs * c2) - c2);
-                nx = x.x + d.x;
-                ny = x.y + d.y;
-                nz = x.z + d.z;
-                turned = true;
+        Kicked k;
+        if constexpr (!kWalls) {
+            k = kick_drift(x, v, f, sc);
+        } else {
+            k.vcx = fmaf(f.x, sc.half_dtm, v.x);
+            k.vcy = fmaf(f.y, sc.half_dtm, v.y);
+            k.vcz = fmaf(f.z, sc.half_dtm, v.z);
+            float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
+            if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
+            float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
+                  nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
+            bool turned = false;
+            if (frozen && sc.wall_kind == 3) {
+                // a turning cylinder turns its frozen layer rigidly by omega dt
+                // about the axis (the particle takes the wall velocity at its
+                // new, grid-rounded position below)
+                float c1, c2;
+                const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
+                if (sc.omega[cyl] != 0.0f) {
+                    const float cs = sc.rot[cyl][0], sn = sc.rot[cyl][1];
+                    const float3 dd = from_axes(sc, fmaf(cs, c1, -sn * c2) - c1, fmaf(sn, c1, cs * c2) - c2);
+                    nx = x.x + dd.x;
+                    ny = x.y + dd.y;
+                    nz = x.z + dd.z;
+                    turned = true;
+                }
             }
-        }
-        const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) &&
-                         isfinite(nz);
-        if (!fin) {
-            bad = true;
-            nx = x.x; ny = x.y; nz = x.z;
-        }
-        esc |= fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
-        nx = rintf(nx * sc.inv_q) * sc.q;
-        ny = rintf(ny * sc.inv_q) * sc.q;
-        nz = rintf(nz * sc.inv_q) * sc.q;
-        if (turned) {                   // the same velocity dpd_set_frozen gives a particle there
-            const float3 u = wall_velocity(nx, ny, nz, sc);
-            vx = u.x; vy = u.y; vz = u.z;
-        }
-        if (kWalls && sc.wall_kind != 0 && live && !frozen && fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
-            // bounce-back: bisection for the sdf's zero along the drift, every
-            // probe on the position grid; the particle goes to the last probe
-            // on the fluid side (the start, t = 0, if none) and its velocity is
-            // reversed in the frame of the wall: v -> 2 u_wall - v
-            const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
-            float lo = 0.0f, hi = 1.0f;
-            for (int it = 0; it < kBounceIters; ++it) {
-                const float mid = 0.5f * (lo + hi);
-                const bool in = wall_sdf(rintf(fmaf(mid, dx, x.x) * sc.inv_q) * sc.q,
-                                         rintf(fmaf(mid, dy, x.y) * sc.inv_q) * sc.q,
-                                         rintf(fmaf(mid, dz, x.z) * sc.inv_q) * sc.q, sc) > 0.0f;
-                lo = in ? lo : mid;
-                hi = in ? mid : hi;
+            k.fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) && isfinite(nz);
+            if (!k.fin) {
+                nx = x.x; ny = x.y; nz = x.z;
             }
-            nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
-            ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
-            nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
-            const float3 u = wall_velocity(nx, ny, nz, sc);           // reversal in the wall's frame
-            vx = fmaf(2.0f, u.x, -vx); vy = fmaf(2.0f, u.y, -vy); vz = fmaf(2.0f, u.z, -vz);
+            k.esc = fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
+            nx = rintf(nx * sc.inv_q) * sc.q;
+            ny = rintf(ny * sc.inv_q) * sc.q;
+            nz = rintf(nz * sc.inv_q) * sc.q;
+            if (turned) {               // the same velocity dpd_set_frozen gives a particle there
+                const float3 u = wall_velocity(nx, ny, nz, sc);
+                vx = u.x; vy = u.y; vz = u.z;
+            }
+            if (sc.wall_kind != 0 && live && !frozen && k.fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
+                // bounce-back: bisection for the sdf's zero along the drift, every
+                // probe on the position grid; the particle goes to the last probe
+                // on the fluid side (the start, t = 0, if none) and its velocity is
+                // reversed in the frame of the wall: v -> 2 u_wall - v
+                const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
+                float lo = 0.0f, hi = 1.0f;
+                for (int it = 0; it < kBounceIters; ++it) {
+                    const float mid = 0.5f * (lo + hi);
+                    const bool in = wall_sdf(rintf(fmaf(mid, dx, x.x) * sc.inv_q) * sc.q,
+                                             rintf(fmaf(mid, dy, x.y) * sc.inv_q) * sc.q,
+                                             rintf(fmaf(mid, dz, x.z) * sc.inv_q) * sc.q, sc) > 0.0f;
+                    lo = in ? lo : mid;
+                    hi = in ? mid : hi;
+                }
+                nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
+                ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
+                nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
+                const float3 u = wall_velocity(nx, ny, nz, sc);           // reversal in the wall's frame
+                vx = fmaf(2.0f, u.x, -vx); vy = fmaf(2.0f, u.y, -vy); vz = fmaf(2.0f, u.z, -vz);
+            }
+            if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
+            if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
+            if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
+            if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
+                k.esc = true;
+                nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
+                ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
+                nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
+            }
+            k.nx = nx; k.ny = ny; k.nz = nz;
+            k.vx = vx; k.vy = vy; k.vz = vz;
         }
-        if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
-        if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
-        if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
-        if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
-            esc = true;
-            nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
-            ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
-            nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
-        }
-        const int c = live ? cell_of(nx, ny, nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
+        bad |= !k.fin;
+        esc |= k.esc;
+        const int c = live ? cell_of(k.nx, k.ny, k.nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
         const ArrivalTicket tk = arrival_issue(c, live, d.count);     // atomic in flight meanwhile
         chunk_add(c, live, d.bsum);
         if (live) {
-            pos_a[i] = make_float4(nx, ny, nz, x.w);
-            vel_a[i] = make_float4(vx, vy, vz, v.w);              // .w: species
+            pos_a[i] = make_float4(k.nx, k.ny, k.nz, x.w);
+            vel_a[i] = make_float4(k.vx, k.vy, k.vz, v.w);          // .w: species
         }
-        if (live && fin && !frozen) {
-            m[0] += (double)vx;
-            m[1] += (double)vy;
-            m[2] += (double)vz;
-            m[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
-            m[4] += (double)vcx * vcx + (double)vcy * vcy + (double)vcz * vcz;
+        if (live && k.fin && !frozen) {
+            add_partials(m, k);
             if (nbins > 0) {
-                const float g = sc.grad_axis == 0 ? x.x : (sc.grad_axis == 1 ? x.y : x.z);
-                int b = (int)(g * sc.grad_scale);
-                b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
-                const float vflow = sc.flow_axis == 0 ? vcx : (sc.flow_axis == 1 ? vcy : vcz);
-                const long long q = llrint((double)vflow * kProfScale);
+                const int b = profile_bin(x, sc);
+                const long long q = profile_units(k.vcx, k.vcy, k.vcz, sc);
                 if (lds_prof) {
                     atomicAdd((unsigned long long*)&s_psum[b], (unsigned long long)q);
                     atomicAdd(&s_pcnt[b], 1);
@@ -705,16 +644,16 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
     }
     if (bad) atomicOr(&d.st->nonfinite, 1);
     if (esc) atomicOr(&d.st->escaped, 1);
-    if (lb == 0 && threadIdx.x == 0) {   // the next force evaluation uses the next step's noise
-        d.st->step += 1;
+    if (lb == 0 && threadIdx.x == 0) {   // the fold adds up this kernel's block partials
+        d.st->fold_count = (unsigned)d.nblk_int;
         d.st->fold_pending = 1;
     }
     // block partials: lane tree inside each wave, then waves in index order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < kPartials; ++k) {
-        const double t = wave_sum(m[k]);
-        if (lane == 0) s_red[wave][k] = t;
+    for (int kk = 0; kk < kPartials; ++kk) {
+        const double t = wave_sum(m[kk]);
+        if (lane == 0) s_red[wave][kk] = t;
     }
     __syncthreads();
     if (threadIdx.x < kPartials) {
@@ -740,7 +679,7 @@ __device__ void fold_stats(const BoxDesc& d)
     DevStats* st = d.st;
     if (!st->fold_pending) return;                 // uniform: written by an earlier kernel
     const double* __restrict__ partials = d.partials;
-    const int nblocks = d.nblk_int;
+    const int nblocks = (int)st->fold_count;
     const StepConst& sc = d.sc;
     // running sums the first thread updates, fetched while the partials load
     long long vir_fx = 0;
@@ -801,6 +740,9 @@ __device__ void fold_stats(const BoxDesc& d)
         st->sum_momentum[1] = sum_m[1] + mass * tot[1];
         st->sum_momentum[2] = sum_m[2] + mass * tot[2];
         st->nsamples = ns + 1;
+        // the step is complete: the next force evaluation takes the next
+        // step's noise (no kernel of this step reads the counter any more)
+        st->step += 1;
         st->fold_pending = 0;
     }
 }

@@ -113,6 +113,8 @@ SIGNATURES = {
     "dpd_get_types": ([_VP, _VP], ctypes.c_int),
     "dpd_build_cells": ([_VP], ctypes.c_int),
     "dpd_step": ([_VP, _I64], ctypes.c_int),
+    "dpd_prepare_steps": ([_VP, _I64], ctypes.c_int),
+    "dpd_time_force": ([_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "dpd_read": ([_VP, ctypes.c_int, _VP, ctypes.c_int], ctypes.c_int),
     "dpd_read_raw": ([_VP, _VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
     "dpd_get_stats": ([_VP, ctypes.POINTER(Stats)], ctypes.c_int),
@@ -121,6 +123,7 @@ SIGNATURES = {
     "dpd_destroy": ([_VP], ctypes.c_int),
     "dpd_profile_steps": ([_VP, _I64, _VP], ctypes.c_int),
     "dpd_last_error": ([], ctypes.c_char_p),
+    "dpd_set_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
     "dpd_philox": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "dpd_box_muller": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
 }
@@ -158,6 +161,12 @@ def _torch():
 
 def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def set_tune_cache(path):
+    """Use (or with None stop using) a JSON autotuner cache file: tuners
+    apply stored tiles without timing and add what they time."""
+    _check(lib().dpd_set_tune_cache(None if path is None else os.fsencode(path)))
 
 
 def make_geom(cells, n):
@@ -339,6 +348,17 @@ class Box:
 
     def step(self, nsteps=1):
         _check(lib().dpd_step(self._h, int(nsteps)))
+
+    def prepare(self, nsteps):
+        """Capture the graphs a step(nsteps) would launch (nothing runs)."""
+        _check(lib().dpd_prepare_steps(self._h, int(nsteps)))
+
+    def time_force(self, reps=20):
+        """Mean ms per launch of the pair-force kernel alone on the current
+        positions (the state does not advance)."""
+        ms = ctypes.c_double()
+        _check(lib().dpd_time_force(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def profile_steps(self, nsteps):
         """Mean device ms per step of each stage (bin, force, virial, integrate),

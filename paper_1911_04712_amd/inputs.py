@@ -58,6 +58,19 @@ def uniform_state(cells, n=None, density=None, kT=1.0, mass=1.0, seed=0, grid=No
     return pos, vel
 
 
+def offgrid_state(cells, n, kT=1.0, mass=1.0, seed=0):
+    """Uniform positions rounded to the nearest FP32 number (not to the
+    position grid of the box: most coordinates below L_max / 2 have bits
+    finer than it), each strictly inside [0, L), and Maxwellian velocities."""
+    cells = tuple(int(c) for c in cells)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = np.asarray(cells, dtype=np.float64)
+    pos = (rng.random((n, 3)) * L).astype(np.float32)
+    top = np.nextafter(L.astype(np.float32), np.float32(0.0))
+    pos = np.minimum(pos, top[None, :])                 # FP32 rounding can reach L itself
+    return pos, _maxwell(rng, n, kT, mass)
+
+
 def clumped_state(cells, n, centre, radius=0.5, kT=1.0, mass=1.0, seed=0, grid=None):
     """n particles packed into a small ball (cells of 40+ particles): the stress
     case for per-cell capacity and work balance."""

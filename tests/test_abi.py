@@ -83,7 +83,11 @@ def test_workspace_bytes_and_validation(lib):
     big = dpd.workspace_bytes((48, 48, 48), 331776)
     assert 0 < small < big
     assert big >= 331776 * 100
-    for bad in [((2, 8, 8), 10), ((8, 8, 8), -1), ((8, 8, 8), 2 ** 31), ((0, 0, 0), 0)]:
+    # the largest particle count keeps the 3 n row offsets of n x 3 arrays in 32 bits
+    nmax = (2 ** 31 - 1) // 3
+    assert dpd.workspace_bytes((4096, 4096, 64), nmax) > 100 * nmax
+    for bad in [((2, 8, 8), 10), ((8, 8, 8), -1), ((8, 8, 8), 2 ** 31), ((0, 0, 0), 0), ((4096, 4096, 64), nmax + 1),
+                ((8, 8, 8), 2 ** 30)]:
         with pytest.raises(dpd.DPDError) as e:
             dpd.workspace_bytes(*bad)
         assert e.value.code == dpd.EINVAL

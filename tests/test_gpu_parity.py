@@ -259,13 +259,38 @@ def test_ten_steps_track_the_oracle():
 # full-size workloads: sampled particles against the oracle
 # ---------------------------------------------------------------------------
 
+def _body_force_sum(pos, w):
+    """Sum of the periodic-Poiseuille body force over the particles (flow
+    axis x, gradient axis y, -f where y <= L_y / 2)."""
+    if w.body_f == 0.0:
+        return 0.0
+    lower = np.count_nonzero(pos[:, 1].astype(np.float64) <= 0.5 * w.cells[1])
+    return w.body_f * (len(pos) - 2 * lower)
+
+
+def _momentum_check(f_gpu, pos, w, label):
+    """Pair forces are exactly antisymmetric fixed-point sums: the forces of
+    the whole box add up to the body-force sum up to the final FP32 rounding
+    of each particle's force."""
+    f = f_gpu.astype(np.float64)
+    tot = f.sum(axis=0)
+    tot[0] -= _body_force_sum(pos, w)
+    bound = np.sum(np.spacing(np.abs(f).astype(np.float32)).astype(np.float64), axis=0)
+    _say(f"[{label}] |sum f - body| = {np.abs(tot)}, rounding bound {bound}")
+    assert np.all(np.abs(tot) <= bound), (label, tot, bound)
+
+
 @pytest.mark.parametrize("name", ["cube48_rho3", "pp192x96x96_rho8"])
 def test_full_size_forces_sampled(name):
+    """Full-size boxes at step 0 on the harness's state and again at a later
+    step on the GPU's own state (the tile shape the benchmark tunes), on 4000
+    sampled particles; the momentum balance over the whole box both times."""
     w = inputs.WORKLOADS[name]
     _say(f"[{name}] generating {w.n} particles")
     pos, vel = inputs.uniform_state(w.cells, n=w.n, kT=w.kT, seed=w.seed)
     params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, body_f=w.body_f, profile_bins=w.profile_bins)
     b = _box(w.cells, pos, vel, params, w.seed)
+    b.tune_tile(reps=2)
     b.step(1)
     f_gpu = b.read(dpd.FORCE)
     rng = np.random.default_rng(15)
@@ -273,10 +298,141 @@ def test_full_size_forces_sampled(name):
     ids = np.arange(w.n, dtype=np.uint32)
     f_orc, s_orc, _ = oracle.forces(pos, vel, ids, w.cells, _orc_params(params), 0, w.seed, which=sample)
     _force_check(f_gpu[sample], f_orc, s_orc, name)
+    _momentum_check(f_gpu, pos, w, name)
     st = b.stats()
     assert st["nonfinite"] == 0 and st["escaped"] == 0
-    # total pair momentum: sum of forces equals the body-force sum to FP32 rounding
+    # a later step on the GPU's own state
+    later = 40
+    b.step(later - 1)
+    pe, ve = b.read(dpd.POS), b.read(dpd.VEL)
+    b.step(1)
+    f_gpu = b.read(dpd.FORCE)
+    f_orc, s_orc, _ = oracle.forces(pe, ve, ids, w.cells, _orc_params(params), later, w.seed, which=sample)
+    _force_check(f_gpu[sample], f_orc, s_orc, f"{name} step {later}")
+    _momentum_check(f_gpu, pe, w, f"{name} step {later}")
+    st = b.stats()
+    assert st["step"] == later + 1 and st["nonfinite"] == 0 and st["escaped"] == 0
     b.close()
+
+
+def test_full_box_forces_cube48_at_step_100():
+    """Every particle of the 48^3 box at step 100, on the GPU's own state,
+    against the oracle over the whole box."""
+    w = inputs.WORKLOADS["cube48_rho3"]
+    pos, vel = inputs.uniform_state(w.cells, n=w.n, kT=w.kT, seed=w.seed)
+    params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt)
+    b = _box(w.cells, pos, vel, params, w.seed)
+    b.step(100)
+    pe, ve = b.read(dpd.POS), b.read(dpd.VEL)
+    b.step(1)
+    f_gpu = b.read(dpd.FORCE)
+    ids = np.arange(w.n, dtype=np.uint32)
+    f_orc, s_orc, _ = oracle.forces(pe, ve, ids, w.cells, _orc_params(params), 100, w.seed)
+    _force_check(f_gpu, f_orc, s_orc, "cube48_rho3 full box, step 100")
+    err = np.linalg.norm(f_gpu.astype(np.float64) - f_orc, axis=1) / np.maximum(np.linalg.norm(f_orc, axis=1), 1e-300)
+    _say(f"[cube48 step 100] relative |df|/|f|: max {err.max():.3e}, p99.99 {np.quantile(err, 0.9999):.3e}")
+    _momentum_check(f_gpu, pe, w, "cube48 step 100")
+    b.close()
+
+
+@pytest.mark.parametrize("cells,rho,seed", [((8, 8, 8), 3.0, 21), ((48, 48, 48), 3.0, 22), ((13, 7, 19), 8.0, 23)])
+def test_cell_list_matches_oracle_at_steps_1_10_100(cells, rho, seed):
+    """The cell list the GPU builds at steps 1, 10 and 100 of its own run
+    equals, bit for bit, the oracle's stable counting sort of the positions
+    in the order the previous step left them."""
+    pos, vel = inputs.uniform_state(cells, density=rho, seed=seed)
+    b = _box(cells, pos, vel, dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01), seed)
+    done = 0
+    for target in (1, 10, 100):
+        if target - 1 > done:
+            b.step(target - 1 - done)
+            done = target - 1
+        if done == 0:
+            ids_prev = np.arange(len(pos), dtype=np.int32)       # the state's own (id) order
+        else:
+            ids_prev = b.read_raw()[0][:, 3].view(np.int32).copy()
+        by_id = b.read(dpd.POS)
+        b.step(1)
+        done += 1
+        p4, _, cs = b.read_raw()
+        order, start = oracle.bin_cells(by_id[ids_prev], cells)
+        np.testing.assert_array_equal(cs, start, err_msg=f"step {target}")
+        np.testing.assert_array_equal(p4[:, 3].view(np.int32), ids_prev[order], err_msg=f"step {target}")
+        np.testing.assert_array_equal(p4[:, :3], by_id[ids_prev][order], err_msg=f"step {target}")
+    b.close()
+
+
+@pytest.mark.parametrize("L", [8, 48, 192])
+def test_offgrid_fp32_inputs(L):
+    """Positions handed over as arbitrary FP32 numbers (finer than the box's
+    position grid q): the library rounds them to q, and its forces are those
+    of the rounded state, within 1e-5 S_i of the oracle on that state.
+    Against the oracle on the raw positions the difference is that bar plus
+    what the rounding (at most q/2 per coordinate) moves the exact forces."""
+    if L == 192:
+        cells, w = (192, 8, 8), inputs.WORKLOADS["pp192x96x96_rho8"]
+    elif L == 48:
+        cells, w = (48, 24, 24), inputs.WORKLOADS["cube48_rho3"]
+    else:
+        cells, w = (8, 8, 8), inputs.WORKLOADS["cube8_rho3"]
+    n = int(round(w.density * cells[0] * cells[1] * cells[2]))
+    pos, vel = inputs.offgrid_state(cells, n, kT=w.kT, seed=30 + L)
+    params = dpd.make_params(a=w.a, gamma=w.gamma, kT=w.kT, dt=w.dt, body_f=w.body_f)
+    b = _box(cells, pos, vel, params, 31)
+    rounded = b.read(dpd.POS)
+    q = dpd.position_grid(cells)
+    d = np.abs(rounded.astype(np.float64) - pos)
+    d = np.minimum(d, np.array(cells, dtype=np.float64) - d)      # a coordinate next to L wraps to 0
+    assert np.all(d <= 0.5 * q)
+    assert np.count_nonzero(rounded != pos) > n // 4              # the inputs were off the grid
+    b.step(1)
+    f_gpu = b.read(dpd.FORCE)
+    ids = np.arange(n, dtype=np.uint32)
+    op = _orc_params(params)
+    f_r, s_r, _ = oracle.forces(rounded, vel, ids, cells, op, 0, 31)
+    _force_check(f_gpu, f_r, s_r, f"off-grid L={L}, rounded state")
+    # against the oracle on the raw positions: the contract is the forces of
+    # the grid-rounded state, so the bar is 1e-5 S_i plus what the rounding
+    # itself moves the exact (FP64) forces, |f_orc(rounded) - f_orc(raw)|
+    f_raw, s_raw, _ = oracle.forces(pos, vel, ids, cells, op, 0, 31)
+    moved = np.linalg.norm(f_r - f_raw, axis=1)
+    err = np.linalg.norm(f_gpu.astype(np.float64) - f_raw, axis=1)
+    _say(f"[off-grid L={L}] raw positions: max |df|/S = {np.max(err / s_raw):.3e}; "
+         f"rounding alone moves the exact forces by up to {np.max(moved / s_raw):.3e} S")
+    assert np.all(err <= TOL_F * s_raw + moved + 1e-30)
+    b.close()
+
+
+def test_profile_bins_match_oracle_statistics():
+    """The time-averaged flow profile of a driven box, GPU against oracle,
+    bin by bin within three combined standard errors (eight blocks each)."""
+    cells, nb = (8, 8, 8), 8
+    pos, vel = inputs.uniform_state(cells, density=3.0, seed=24)
+    params = dpd.make_params(a=25.0, gamma=6.75, kT=1.0, dt=0.04, body_f=0.2, profile_bins=nb)
+    b = _box(cells, pos, vel, params, 24)
+    b.step(600)
+    gp = []
+    for _ in range(8):
+        b.reset_accumulators()
+        b.step(400)
+        sv, cn = b.profile()
+        gp.append(sv / cn)
+    b.close()
+    x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    ids = np.arange(len(x), dtype=np.uint32)
+    op = _orc_params(params)
+    oracle.step(x, v, ids, cells, op, 24, 0, 600, want_diag=False)
+    op_ = []
+    for k in range(8):
+        _, ps, pc, _ = oracle.step(x, v, ids, cells, op, 24, 600 + 400 * k, 400, nbins=nb, want_diag=False)
+        op_.append(ps / pc)
+    gp, op_ = np.array(gp), np.array(op_)
+    gm, ge = gp.mean(axis=0), gp.std(axis=0, ddof=1) / math.sqrt(8)
+    om, oe = op_.mean(axis=0), op_.std(axis=0, ddof=1) / math.sqrt(8)
+    z = np.abs(gm - om) / np.hypot(ge, oe)
+    _say(f"profile GPU {np.round(gm, 4)}\n        orc {np.round(om, 4)}\n        z {np.round(z, 2)}")
+    assert np.all(gm[: nb // 2] < 0) and np.all(gm[nb // 2:] > 0)
+    assert np.all(z < 3.0), z
 
 
 # ---------------------------------------------------------------------------
