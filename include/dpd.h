@@ -360,6 +360,41 @@ int dpd_destroy(dpd_box box);
  * timed stages).  The steps advance the box like dpd_step.  Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
 
+/* ---- a run that allocates nothing -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The box
+ * lives in an array of DPD_STATIC_WS_BYTES that the library holds in device
+ * memory (one per GPU it runs on, kept until the process ends), instead of a
+ * caller workspace. */
+
+/* Size of the library's static per-GPU machine array: boxes whose
+ * dpd_workspace_bytes is at most this (a 48^3 box at density 3 needs 40 MB). */
+#define DPD_STATIC_WS_BYTES (64u * 1024u * 1024u)
+
+/* One whole run, equal bit for bit to dpd_create (on any workspace) +
+ * dpd_set_params + dpd_set_seed + dpd_set_state(pos_n3, vel_n3, DPD_DEVICE)
+ * + dpd_set_step(step0) + dpd_step(nsteps) + dpd_read(DPD_POS / DPD_VEL,
+ * DPD_DEVICE) + dpd_get_stats + dpd_destroy, with the box in the static
+ * array of the current GPU.
+ *   pos_n3, vel_n3:          device, n x 3 floats, row = id (inputs; as for
+ *                            dpd_set_state: pos in [0, L), rounded to the grid)
+ *   pos_out_n3, vel_out_n3:  device, n x 3 floats: x^{step0+nsteps} and
+ *                            v^{step0+nsteps-1/2}; may not overlap the inputs
+ *   stats:                   host, may be NULL
+ * One species, no frozen particles, the default tile.  The steps are
+ * launched directly on hip_stream (no graph), and the call synchronises it.
+ * It calls no hipMalloc, hipFree or other allocating routine.  Errors:
+ * DPD_EINVAL (geometry, params, null arrays, positions), DPD_ENOMEM when the
+ * box needs more than DPD_STATIC_WS_BYTES (checked before any GPU call),
+ * DPD_ENONFINITE as dpd_get_stats (outputs still written), DPD_EDEVICE.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one GPU, from several threads or streams, race and must not be
+ * made. */
+int dpd_run_static(const dpd_geom* geom, const dpd_params* params, uint64_t seed, uint64_t step0,
+                   const float* pos_n3, const float* vel_n3, int64_t nsteps, float* pos_out_n3,
+                   float* vel_out_n3, dpd_stats* stats, void* hip_stream);
+
 /* ---- batches of independent boxes ------------------------------------------
  * A batch steps many boxes (uneven sizes, own parameters and seeds) with one
  * launch per kernel for all of them, and a run of up to 1024 steps is a

@@ -615,6 +615,42 @@ std::string box_tune_part(const dpd_box_s* b)
 
 std::string tune_key_prefix(hipStream_t s) { return arch_name(s) + "|" DPD_KERNEL_REV "|"; }
 
+// Lay a validated geometry out in `dev_ws` (large enough, 256-byte aligned)
+// and clear the counters, accumulators and flags that the step kernels
+// expect at zero.  The body of dpd_create, shared with dpd_run_static.
+int box_init(dpd_box_s* b, const dpd_geom* geom, void* dev_ws, void* hip_stream)
+{
+    const int64_t nc = (int64_t)geom->cells[0] * geom->cells[1] * geom->cells[2];
+    const dpd::Layout lay = dpd::make_layout(geom->n, nc);
+    b->geom = *geom;
+    b->n = (int)geom->n;
+    b->nc = (int)nc;
+    for (int k = 0; k < 3; ++k) {
+        b->cells[k] = geom->cells[k];
+        b->L[k] = (float)geom->cells[k];
+    }
+    b->q = grid_of(geom);
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (char*)dev_ws;
+    b->lay = lay;
+    b->d_desc = (dpd::BoxDesc*)(b->ws + lay.desc);
+    b->d_pre = (int*)(b->ws + lay.pre);
+    b->flags = (int*)(b->ws + lay.flags);
+    b->out = (float*)(b->ws + lay.out);
+    const int rc = push_desc(b);
+    if (rc != DPD_OK) return rc;
+    hipError_t e = dpd::launch_fill_i32(b->hd.count, 0, nc, b->stream);
+    if (e == hipSuccess) e = dpd::launch_fill_i32(b->hd.bsum, 0, b->hd.nsub, b->stream);
+    if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->hd.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
+    if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->hd.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
+    if (e == hipSuccess) e = dpd::launch_fill_i32(b->flags, 0, 4, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_create: %s", hipGetErrorString(e));
+    return DPD_OK;
+}
+
+
+
 }  // namespace
 
 extern "C" {
@@ -648,33 +684,7 @@ int dpd_create(const dpd_geom* geom, void* dev_ws, size_t ws_bytes, void* hip_st
         return fail(DPD_ENOMEM, "dpd_create: workspace of %zu bytes, %zu needed", ws_bytes, lay.total);
     dpd_box_s* b = new (std::nothrow) dpd_box_s();
     if (!b) return fail(DPD_ENOMEM, "dpd_create: host allocation failed");
-    b->geom = *geom;
-    b->n = (int)geom->n;
-    b->nc = (int)nc;
-    for (int k = 0; k < 3; ++k) {
-        b->cells[k] = geom->cells[k];
-        b->L[k] = (float)geom->cells[k];
-    }
-    b->q = grid_of(geom);
-    b->stream = (hipStream_t)hip_stream;
-    b->ws = (char*)dev_ws;
-    b->lay = lay;
-    b->d_desc = (dpd::BoxDesc*)(b->ws + lay.desc);
-    b->d_pre = (int*)(b->ws + lay.pre);
-    b->flags = (int*)(b->ws + lay.flags);
-    b->out = (float*)(b->ws + lay.out);
-    int rc = push_desc(b);
-    hipError_t e = hipSuccess;
-    if (rc == DPD_OK) {
-        e = dpd::launch_fill_i32(b->hd.count, 0, nc, b->stream);
-        if (e == hipSuccess) e = dpd::launch_fill_i32(b->hd.bsum, 0, b->hd.nsub, b->stream);
-        if (e == hipSuccess) e = dpd::launch_fill_i32((int*)b->hd.st, 0, (int64_t)(sizeof(dpd::DevStats) / 4), b->stream);
-        if (e == hipSuccess)
-            e = dpd::launch_fill_i32((int*)b->hd.profile, 0, (int64_t)dpd::kProfileMaxBins * 4, b->stream);
-        if (e == hipSuccess) e = dpd::launch_fill_i32(b->flags, 0, 4, b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) rc = fail(DPD_EDEVICE, "dpd_create: %s", hipGetErrorString(e));
-    }
+    const int rc = box_init(b, geom, dev_ws, hip_stream);
     if (rc != DPD_OK) {
         delete b;
         return rc;
@@ -1295,6 +1305,94 @@ int dpd_destroy(dpd_box b)
     delete b;
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_destroy: %s", hipGetErrorString(e));
     return DPD_OK;
+}
+
+}  // extern "C"
+
+// ---- a box in the library's own device memory (dpd_run_static) -------------
+//
+// Each GPU the library runs on holds one copy of this array until the process
+// ends.  In host code its name is only a host-side stand-in: the device
+// address of the current GPU's copy comes from hipGetSymbolAddress, once per
+// device, and only that address is ever handed to a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[DPD_STATIC_WS_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`.
+int scratch_ptr(void** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DPD_EDEVICE, "dpd_run_static: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DPD_EDEVICE, "dpd_run_static: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DPD_OK;
+}
+
+// The run of dpd_run_static on box b laid out in the static array.
+int run_static_on(dpd_box_s* b, const dpd_params* params, uint64_t seed, uint64_t step0, const float* pos_n3,
+                  const float* vel_n3, int64_t nsteps, float* pos_out_n3, float* vel_out_n3, dpd_stats* stats)
+{
+    int rc = dpd_set_params(b, params);
+    if (rc == DPD_OK) rc = dpd_set_seed(b, seed);
+    if (rc == DPD_OK) rc = dpd_set_state(b, pos_n3, vel_n3, DPD_DEVICE);
+    if (rc == DPD_OK && step0 != 0) rc = dpd_set_step(b, step0);
+    if (rc != DPD_OK) return rc;
+    if (nsteps > 0) {
+        // the steps of dpd_step, launched directly (instantiating a graph
+        // would allocate), then the fold of the last step's reductions
+        HIPCHK(enqueue_steps(b->lp, nsteps, b->stream));
+        HIPCHK(dpd::launch_fold(b->lp, b->stream));
+        b->keys_valid = true;
+        b->have_force = true;
+    }
+    if ((rc = dpd_read(b, DPD_POS, pos_out_n3, DPD_DEVICE)) || (rc = dpd_read(b, DPD_VEL, vel_out_n3, DPD_DEVICE)))
+        return rc;
+    if (stats) return dpd_get_stats(b, stats);
+    return sync_box(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_run_static(const dpd_geom* geom, const dpd_params* params, uint64_t seed, uint64_t step0,
+                   const float* pos_n3, const float* vel_n3, int64_t nsteps, float* pos_out_n3, float* vel_out_n3,
+                   dpd_stats* stats, void* hip_stream)
+{
+    if (!geom || !params) return fail(DPD_EINVAL, "dpd_run_static: null geometry or params");
+    if (!geom_ok(geom)) return fail(DPD_EINVAL, "dpd_run_static: invalid geometry (cells in 3..4096, 0 <= n <= (2^31 - 1) / 3)");
+    if (nsteps < 0) return fail(DPD_EINVAL, "dpd_run_static: nsteps < 0");
+    const int64_t nc = (int64_t)geom->cells[0] * geom->cells[1] * geom->cells[2];
+    const size_t need = dpd::make_layout(geom->n, nc).total;
+    if (need > (size_t)DPD_STATIC_WS_BYTES)
+        return fail(DPD_ENOMEM, "dpd_run_static: the box needs %zu bytes of workspace, more than the %zu bytes of "
+                    "the library's static array (DPD_STATIC_WS_BYTES); use dpd_create with a workspace",
+                    need, (size_t)DPD_STATIC_WS_BYTES);
+    if (geom->n > 0 && (!pos_n3 || !vel_n3 || !pos_out_n3 || !vel_out_n3))
+        return fail(DPD_EINVAL, "dpd_run_static: null particle array");
+    void* ws = nullptr;
+    int rc = scratch_ptr(&ws);
+    if (rc) return rc;
+    dpd_box_s b;                        // host object only: nothing of it outlives the call
+    rc = box_init(&b, geom, ws, hip_stream);
+    if (rc == DPD_OK)
+        rc = run_static_on(&b, params, seed, step0, pos_n3, vel_n3, nsteps, pos_out_n3, vel_out_n3, stats);
+    const hipError_t e = hipStreamSynchronize(b.stream);
+    if (rc == DPD_OK && e != hipSuccess) rc = fail(DPD_EDEVICE, "dpd_run_static: %s", hipGetErrorString(e));
+    return rc;
 }
 
 // ---- batches ------------------------------------------------------------------

@@ -126,7 +126,12 @@ SIGNATURES = {
     "dpd_set_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
     "dpd_philox": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "dpd_box_muller": ([_VP, _VP, _I64, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "dpd_run_static": ([ctypes.POINTER(Geom), ctypes.POINTER(Params), ctypes.c_uint64, ctypes.c_uint64, _VP, _VP,
+                        _I64, _VP, _VP, ctypes.POINTER(Stats), _VP], ctypes.c_int),
 }
+
+# Bytes of the library's static per-GPU machine array (DPD_STATIC_WS_BYTES).
+STATIC_WS_BYTES = 64 * 1024 * 1024
 
 _lib = None
 
@@ -533,6 +538,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def run_static(cells, pos, vel, params, seed, nsteps, step0=0, pos_out=None, vel_out=None, allow_nonfinite=False):
+    """One whole run in the library's static per-GPU machine array
+    (dpd_run_static: no device allocation by the library).  pos, vel: torch
+    CUDA float32 tensors (n, 3), row = id (numpy arrays are copied to the
+    GPU first); pos_out, vel_out: torch CUDA float32 (n, 3) tensors, made if
+    None.  Returns (pos_out, vel_out, stats)."""
+    torch = _torch()
+
+    def dev(a):
+        if isinstance(a, torch.Tensor) and a.is_cuda:
+            return a.to(torch.float32).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32).reshape(-1, 3), device="cuda")
+
+    p, v = dev(pos), dev(vel)
+    n = p.shape[0]
+    po = torch.empty((n, 3), dtype=torch.float32, device="cuda") if pos_out is None else pos_out
+    vo = torch.empty((n, 3), dtype=torch.float32, device="cuda") if vel_out is None else vel_out
+    for t in (po, vo):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (n, 3)):
+            raise ValueError("pos_out / vel_out must be contiguous CUDA float32 tensors of shape (n, 3)")
+    st = Stats()
+    prm = params if params is not None else make_params()
+    rc = lib().dpd_run_static(ctypes.byref(make_geom(cells, n)), ctypes.byref(prm), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                              int(step0), ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(nsteps),
+                              ctypes.c_void_p(po.data_ptr()), ctypes.c_void_p(vo.data_ptr()), ctypes.byref(st),
+                              _stream_ptr(torch))
+    if not (allow_nonfinite and rc == ENONFINITE):
+        _check(rc)
+    return po, vo, st.as_dict()
 
 
 def philox(ctr4, key2):

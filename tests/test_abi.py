@@ -112,3 +112,28 @@ def test_null_box_calls_fail_cleanly(lib):
     s = dpd.Stats()
     assert lib.dpd_get_stats(None, ctypes.byref(s)) == dpd.EINVAL
     assert lib.dpd_philox(None, None, 4, None, dpd.HOST, None) == dpd.EINVAL
+
+
+def test_run_static_rejects_before_any_device_call(lib):
+    """dpd_run_static checks its arguments and the static array's size on
+    the host, before it touches a GPU."""
+    p = dpd.make_params()
+    st = dpd.Stats()
+    fake = ctypes.c_void_p(1 << 20)       # never dereferenced: every call below fails first
+
+    def run(geom, params=p, nsteps=1, arrays=fake):
+        return lib.dpd_run_static(ctypes.byref(geom) if geom is not None else None,
+                                  ctypes.byref(params) if params is not None else None, 1, 0, arrays, arrays,
+                                  nsteps, arrays, arrays, ctypes.byref(st), None)
+
+    # 64 MiB holds a 48^3 box at density 3, not one at density 8
+    assert dpd.workspace_bytes((48, 48, 48), 331776) <= dpd.STATIC_WS_BYTES
+    assert dpd.workspace_bytes((48, 48, 48), 884736) > dpd.STATIC_WS_BYTES
+    assert run(dpd.make_geom((48, 48, 48), 884736)) == dpd.ENOMEM
+    assert b"static array" in lib.dpd_last_error()
+    assert run(dpd.make_geom((2, 8, 8), 10)) == dpd.EINVAL
+    assert run(None) == dpd.EINVAL
+    assert run(dpd.make_geom((8, 8, 8), 10), params=None) == dpd.EINVAL
+    assert run(dpd.make_geom((8, 8, 8), 10), nsteps=-1) == dpd.EINVAL
+    assert run(dpd.make_geom((8, 8, 8), 10), arrays=None) == dpd.EINVAL
+    assert b"null particle array" in lib.dpd_last_error()
