@@ -19,6 +19,7 @@
 
 #include "dpd.h"
 #include "dpd_internal.hpp"
+#include "dpd_runtime.hpp"
 
 static_assert(DPD_FLAG_VIRIAL == dpd::kFlagVirial, "flag mismatch");
 static_assert(DPD_FLAG_REFERENCE_FORCE == dpd::kFlagReference, "flag mismatch");
@@ -208,6 +209,7 @@ struct dpd_box_s {
 
 struct dpd_batch_s {
     std::vector<dpd_box_s*> boxes;
+    int capacity = 0;          // most boxes the device tables hold
     hipStream_t stream = nullptr;
     dpd::BoxDesc* d_desc = nullptr;
     int* d_pre = nullptr;
@@ -215,7 +217,15 @@ struct dpd_batch_s {
     dpd::LaunchPlan lp{};
     GraphCache graphs;
     bool graph_dirty = true;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;     // the last run's end (boxes on other streams wait for it)
+    hipEvent_t pending = nullptr;  // work queued on a box's own stream (the run waits for it)
+    // pinned staging of the tables, two buffers used in turn: the copy from
+    // one may still be queued behind a running step while the other is filled
+    char* stage[2] = {nullptr, nullptr};
+    size_t stage_bytes[2] = {0, 0};
+    hipEvent_t stage_done[2] = {nullptr, nullptr};
+    bool stage_used[2] = {false, false};
+    int stage_next = 0;
 };
 
 namespace {
@@ -648,7 +658,6 @@ int box_init(dpd_box_s* b, const dpd_geom* geom, void* dev_ws, void* hip_stream)
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_create: %s", hipGetErrorString(e));
     return DPD_OK;
 }
-
 
 
 }  // namespace
@@ -1250,22 +1259,7 @@ int dpd_get_stats(dpd_box b, dpd_stats* out)
     dpd::DevStats s;
     HIPCHK(hipMemcpyAsync(&s, b->hd.st, sizeof s, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    std::memset(out, 0, sizeof *out);
-    for (int k = 0; k < 3; ++k) {
-        out->momentum[k] = s.last[k];
-        out->sum_momentum[k] = s.sum_momentum[k];
-    }
-    out->ke_half = s.last[3];
-    out->ke_centred = s.last[4];
-    out->kT_centred = s.last_kT_centred;
-    out->virial = s.last_virial;
-    out->pressure = s.last_pressure;
-    out->sum_kT_centred = s.sum_kT_centred;
-    out->sum_pressure = s.sum_pressure;
-    out->nsamples = s.nsamples;
-    out->step = s.step;
-    out->nonfinite = s.nonfinite;
-    out->escaped = s.escaped;
+    dpd::stats_from_device(s, out);
     if (s.nonfinite) return fail(DPD_ENONFINITE, "dpd_get_stats: non-finite value seen");
     return DPD_OK;
 }
@@ -1449,10 +1443,39 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.fuse = !walls;
     if (changed) bt->graph_dirty = true;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));
-    HIPCHK(hipMemcpyAsync(bt->d_desc, h.data(), (size_t)nb * sizeof(dpd::BoxDesc), hipMemcpyHostToDevice, bt->stream));
-    HIPCHK(hipMemcpyAsync(bt->d_pre, bt->pre.data(), bt->pre.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream));
-    HIPCHK(hipStreamSynchronize(bt->stream));
+    // the tables go through pinned memory, so the copies are queued behind
+    // the work already on the batch stream without the host waiting for it
+    const size_t desc_bytes = (size_t)nb * sizeof(dpd::BoxDesc), pre_bytes = bt->pre.size() * sizeof(int);
+    const int k = bt->stage_next;
+    bt->stage_next ^= 1;
+    if (bt->stage_used[k]) HIPCHK(hipEventSynchronize(bt->stage_done[k]));   // its last copy has run
+    if (bt->stage_bytes[k] < desc_bytes + pre_bytes) {
+        if (bt->stage[k]) HIPCHK(hipHostFree(bt->stage[k]));
+        bt->stage[k] = nullptr;
+        bt->stage_bytes[k] = 0;
+        HIPCHK(hipHostMalloc((void**)&bt->stage[k], desc_bytes + pre_bytes, hipHostMallocDefault));
+        bt->stage_bytes[k] = desc_bytes + pre_bytes;
+    }
+    std::memcpy(bt->stage[k], h.data(), desc_bytes);
+    std::memcpy(bt->stage[k] + desc_bytes, bt->pre.data(), pre_bytes);
+    HIPCHK(hipMemcpyAsync(bt->d_desc, bt->stage[k], desc_bytes, hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(hipMemcpyAsync(bt->d_pre, bt->stage[k] + desc_bytes, pre_bytes, hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(hipEventRecord(bt->stage_done[k], bt->stream));
+    bt->stage_used[k] = true;
     return DPD_OK;
+}
+
+// Release what a batch holds (after its stream has drained).
+void batch_free(dpd_batch_s* bt)
+{
+    bt->graphs.release();
+    for (int k = 0; k < 2; ++k) {
+        if (bt->stage[k]) (void)hipHostFree(bt->stage[k]);
+        if (bt->stage_done[k]) (void)hipEventDestroy(bt->stage_done[k]);
+    }
+    if (bt->done) (void)hipEventDestroy(bt->done);
+    if (bt->pending) (void)hipEventDestroy(bt->pending);
+    delete bt;
 }
 
 }  // namespace
@@ -1478,15 +1501,25 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
     dpd_batch_s* bt = new (std::nothrow) dpd_batch_s();
     if (!bt) return fail(DPD_ENOMEM, "dpd_batch_create: host allocation failed");
     bt->boxes.assign(boxes, boxes + nboxes);
+    // the tables are laid out for as many boxes as the workspace holds, so a
+    // batch can later take other boxes (the request server's use)
+    int cap = nboxes;
+    for (int step = 32768; step > 0; step >>= 1) {
+        size_t b = 0;
+        if (cap + step <= 65536 && dpd_batch_workspace_bytes(cap + step, &b) == DPD_OK && b <= ws_bytes) cap += step;
+    }
+    bt->capacity = cap;
     bt->stream = (hipStream_t)hip_stream;
     bt->d_desc = (dpd::BoxDesc*)dev_ws;
-    bt->d_pre = (int*)((char*)dev_ws + align256((size_t)nboxes * sizeof(dpd::BoxDesc)));
+    bt->d_pre = (int*)((char*)dev_ws + align256((size_t)cap * sizeof(dpd::BoxDesc)));
     bt->lp.lds_force = -1;
     hipError_t e = hipEventCreateWithFlags(&bt->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->pending, hipEventDisableTiming);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&bt->stage_done[k], hipEventDisableTiming);
     int rc = e == hipSuccess ? batch_refresh(bt) : fail(DPD_EDEVICE, "dpd_batch_create: %s", hipGetErrorString(e));
     if (rc) {
-        if (bt->done) (void)hipEventDestroy(bt->done);
-        delete bt;
+        (void)hipStreamSynchronize(bt->stream);
+        batch_free(bt);
         return rc;
     }
     *out = bt;
@@ -1640,7 +1673,12 @@ int dpd_batch_step(dpd_batch bt, int64_t nsteps)
         return fail(DPD_ESTATE, "dpd_batch_step: %zu of %zu boxes hold a bare cell list; step them once alone",
                     nbinned, bt->boxes.size());
     if (nsteps == 0) return DPD_OK;
-    for (dpd_box_s* b : bt->boxes) HIPCHK(hipStreamSynchronize(b->stream));
+    // the run waits (on the device) for what is queued on the boxes' own streams
+    for (dpd_box_s* b : bt->boxes)
+        if (b->stream != bt->stream) {
+            HIPCHK(hipEventRecord(bt->pending, b->stream));
+            HIPCHK(hipStreamWaitEvent(bt->stream, bt->pending, 0));
+        }
     int rc = batch_refresh(bt);
     if (rc) return rc;
     // One graph holds the whole run (up to kBatchGraphMax steps), so a run is
@@ -1667,7 +1705,7 @@ int dpd_batch_step(dpd_batch bt, int64_t nsteps)
     // later work on each box's own stream waits for the batch
     HIPCHK(hipEventRecord(bt->done, bt->stream));
     for (dpd_box_s* b : bt->boxes) {
-        HIPCHK(hipStreamWaitEvent(b->stream, bt->done, 0));
+        if (b->stream != bt->stream) HIPCHK(hipStreamWaitEvent(b->stream, bt->done, 0));
         b->keys_valid = true;
         b->have_force = true;
         b->binned = false;
@@ -1679,9 +1717,7 @@ int dpd_batch_destroy(dpd_batch bt)
 {
     if (!bt) return DPD_OK;
     hipError_t e = hipStreamSynchronize(bt->stream);
-    bt->graphs.release();
-    if (bt->done) (void)hipEventDestroy(bt->done);
-    delete bt;
+    batch_free(bt);
     if (e != hipSuccess) return fail(DPD_EDEVICE, "dpd_batch_destroy: %s", hipGetErrorString(e));
     return DPD_OK;
 }
@@ -1709,3 +1745,74 @@ int dpd_box_muller(const uint32_t* w0, const uint32_t* w1, int64_t n, float* xi,
 }
 
 }  // extern "C"
+
+// ---- calls of the request server that do not synchronise (dpd_runtime.hpp) ----
+
+namespace dpd {
+
+int box_set_stream(dpd_box b, hipStream_t s)
+{
+    if (!b) return fail(DPD_EINVAL, "box_set_stream: null box");
+    b->stream = s;
+    b->graph_dirty = true;             // graphs are captured from the box stream's work
+    return DPD_OK;
+}
+
+int box_enqueue_results(dpd_box b, float* pos_n3, float* vel_n3, DevStats* dev_stats)
+{
+    if (!b || !dev_stats || (b->n > 0 && (!pos_n3 || !vel_n3)))
+        return fail(DPD_EINVAL, "box_enqueue_results: null argument");
+    if (!b->have_state) return fail(DPD_ESTATE, "box_enqueue_results: no state loaded");
+    const BoxDesc& d = b->hd;
+    const size_t bytes = (size_t)b->n * 3 * sizeof(float);
+    if (b->n > 0) {
+        // both quantities pass through the box's staging rows in turn (stream order)
+        HIPCHK(launch_to_rows(d.pos_a, nullptr, 0.0f, d.pos_a, b->n, b->out, b->stream));
+        HIPCHK(hipMemcpyAsync(pos_n3, b->out, bytes, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(launch_to_rows(d.vel_a, nullptr, 0.0f, d.pos_a, b->n, b->out, b->stream));
+        HIPCHK(hipMemcpyAsync(vel_n3, b->out, bytes, hipMemcpyDeviceToHost, b->stream));
+    }
+    HIPCHK(hipMemcpyAsync(dev_stats, d.st, sizeof(DevStats), hipMemcpyDeviceToHost, b->stream));
+    return DPD_OK;
+}
+
+void stats_from_device(const DevStats& s, dpd_stats* out)
+{
+    std::memset(out, 0, sizeof *out);
+    for (int k = 0; k < 3; ++k) {
+        out->momentum[k] = s.last[k];
+        out->sum_momentum[k] = s.sum_momentum[k];
+    }
+    out->ke_half = s.last[3];
+    out->ke_centred = s.last[4];
+    out->kT_centred = s.last_kT_centred;
+    out->virial = s.last_virial;
+    out->pressure = s.last_pressure;
+    out->sum_kT_centred = s.sum_kT_centred;
+    out->sum_pressure = s.sum_pressure;
+    out->nsamples = s.nsamples;
+    out->step = s.step;
+    out->nonfinite = s.nonfinite;
+    out->escaped = s.escaped;
+}
+
+void box_release(dpd_box b)
+{
+    if (!b) return;
+    b->graphs.release();
+    delete b;
+}
+
+int batch_set_boxes(dpd_batch bt, const dpd_box* boxes, int32_t nboxes)
+{
+    if (!bt || (nboxes > 0 && !boxes)) return fail(DPD_EINVAL, "batch_set_boxes: null argument");
+    if (nboxes < 1 || nboxes > bt->capacity)
+        return fail(DPD_EINVAL, "batch_set_boxes: %d boxes, the tables hold 1..%d", nboxes, bt->capacity);
+    for (int i = 0; i < nboxes; ++i)
+        if (!boxes[i]) return fail(DPD_EINVAL, "batch_set_boxes: null box %d", i);
+    bt->boxes.assign(boxes, boxes + nboxes);
+    bt->graph_dirty = true;
+    return batch_refresh(bt);
+}
+
+}  // namespace dpd

@@ -169,7 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restri
 // ---------------------------------------------------------------------------
 constexpr int kQueueLive = 192; // per-wave hit queue: < 64 pending + up to 2 x 64 new ...
 constexpr int kQueue = 256;     // ... then 64 slots that lanes without a hit write to
-constexpr int kRuns = 14;       // candidate runs of one home cell
 
 // Inclusive prefix sum inside each row of 16 lanes (DPP row shifts).
 __device__ __forceinline__ int row16_incl_scan(int v)
@@ -234,12 +233,16 @@ constexpr int kProfSlots = 64;  // flow-profile slabs one tile sums in LDS befor
 // position and velocity go to pos_a / vel_a, its next cell and arrival slot
 // to keyslot and the cell counters, and the tile's FP64 sums (fixed order:
 // lanes, then waves) to its own entry of `partials`, which the fold adds
-// up in tile order.  src(rw, k, x, v, f) gives particle k of tile row rw:
-// its position x^n, stored velocity (w = species) and force.  scr is LDS
-// the kernel no longer uses (at least kProfSlots * 12 + waves * 40 bytes).
-// Every thread of the workgroup calls it.
+// up in tile order.  The nt tile particles are taken flat, thread k with
+// particles k, k + threads, ..., so a tile of a few hundred particles is one
+// pass of the whole workgroup with one round trip of the arrival atomics;
+// the row of a particle comes from a binary search over the rows' tile
+// starts.  src(rw, k, x, v, f) gives particle k of tile row rw: its position
+// x^n, stored velocity (w = species) and force.  scr is LDS the kernel no
+// longer uses (at least kProfSlots * 12 + waves * 40 bytes).  Every thread
+// of the workgroup calls it.
 template <bool kFuse, int kThreads, typename Src>
-__device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* rows, int nrows, int o_grad,
+__device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* rows, int nrows, int nt, int o_grad,
                                            unsigned char* scr, Src src)
 {
     constexpr int nw = kThreads >> 6;
@@ -257,48 +260,53 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
         }
         __syncthreads();
     }
+    int top = 1;                                        // binary search over the rows' tile starts
+    while (top * 2 <= nrows) top *= 2;
     double m[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false, esc = false;
-    for (int r = wave; r < nrows; r += nw) {
-        const int4 rw = rows[r];
-        for (int k0 = 0; k0 < rw.y; k0 += 64) {            // wave-uniform: every lane reaches the atomics
-            const int k = k0 + lane;
-            const bool live = k < rw.y;
-            const int g = rw.z + k;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
+    for (int ti0 = wave * 64; ti0 < nt; ti0 += kThreads) {   // wave-uniform: every lane reaches the atomics
+        const int ti = ti0 + lane;
+        const bool live = ti < nt;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
+        int g = 0;
+        if (live) {
+            int r = 0;
+            for (int st = top; st > 0; st >>= 1)
+                if (r + st < nrows && rows[r + st].w <= ti) r += st;
+            const int4 rw = rows[r];
+            const int k = ti - rw.w;
+            g = rw.z + k;
+            src(rw, k, x, v, f);
+            d.force[g] = f;
+        }
+        if constexpr (kFuse) {
+            const Kicked kk = kick_drift(x, v, f, sc);
+            bad |= !kk.fin;
+            esc |= kk.esc;
+            const int c = live ? cell_of(kk.nx, kk.ny, kk.nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
+            const ArrivalTicket tk = arrival_issue(c, live, d.count);   // atomic in flight meanwhile
+            chunk_add(c, live, d.bsum);
             if (live) {
-                src(rw, k, x, v, f);
-                d.force[g] = f;
+                d.pos_a[g] = make_float4(kk.nx, kk.ny, kk.nz, x.w);
+                d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, v.w);
             }
-            if constexpr (kFuse) {
-                const Kicked kk = kick_drift(x, v, f, sc);
-                bad |= !kk.fin;
-                esc |= kk.esc;
-                const int c = live ? cell_of(kk.nx, kk.ny, kk.nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
-                const ArrivalTicket tk = arrival_issue(c, live, d.count);   // atomic in flight meanwhile
-                chunk_add(c, live, d.bsum);
-                if (live) {
-                    d.pos_a[g] = make_float4(kk.nx, kk.ny, kk.nz, x.w);
-                    d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, v.w);
-                }
-                if (live && kk.fin) {
-                    add_partials(m, kk);
-                    if (nbins > 0) {
-                        const int b = profile_bin(x, sc);
-                        const long long q = profile_units(kk.vcx, kk.vcy, kk.vcz, sc);
-                        const int sl = b - blo;
-                        if (sl >= 0 && sl < kProfSlots) {
-                            atomicAdd((unsigned long long*)&p_sum[sl], (unsigned long long)q);
-                            atomicAdd(&p_cnt[sl], 1);
-                        } else {
-                            atomicAdd((unsigned long long*)&d.profile[2 * b], (unsigned long long)q);
-                            atomicAdd((unsigned long long*)&d.profile[2 * b + 1], 1ull);
-                        }
+            if (live && kk.fin) {
+                add_partials(m, kk);
+                if (nbins > 0) {
+                    const int b = profile_bin(x, sc);
+                    const long long q = profile_units(kk.vcx, kk.vcy, kk.vcz, sc);
+                    const int sl = b - blo;
+                    if (sl >= 0 && sl < kProfSlots) {
+                        atomicAdd((unsigned long long*)&p_sum[sl], (unsigned long long)q);
+                        atomicAdd(&p_cnt[sl], 1);
+                    } else {
+                        atomicAdd((unsigned long long*)&d.profile[2 * b], (unsigned long long)q);
+                        atomicAdd((unsigned long long*)&d.profile[2 * b + 1], 1ull);
                     }
                 }
-                const int slot = arrival_finish(tk, live);
-                if (live) d.keyslot[g] = make_int2(c, slot);
             }
+            const int slot = arrival_finish(tk, live);
+            if (live) d.keyslot[g] = make_int2(c, slot);
         }
     }
     if constexpr (kFuse) {
@@ -434,10 +442,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
                 force[rw.z + k] = gather_force_one<kSp>(rw.z + k, pos, vel, cell_start, fc, step, bad);
         }
         if (bad) atomicOr(nonfinite, 1);
-        // the write-out visits the particles with the same lanes, so each
-        // lane reads back the force it wrote
+        // the write-out takes the particles in another order: the barrier
+        // makes every force written above visible to the whole workgroup
+        __syncthreads();
         if constexpr (kFuse)
-            write_tile<kFuse, kThreads>(d, t, rows, nrows, o_grad, scr,
+            write_tile<kFuse, kThreads>(d, t, rows, nrows, nt, o_grad, scr,
                                         [&](const int4& rw, int k, float4& x, float4& v, float4& f) {
                                             const int g = rw.z + k;
                                             x = pos[g];
@@ -671,7 +680,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
     // 5. each tile particle's force is written once, in cell order (a tile
     //    particle is staged without an image shift, so sp holds x^n); with
     //    kFuse its kick-drift follows
-    write_tile<kFuse, kThreads>(d, t, rows, nrows, o_grad, scr,
+    write_tile<kFuse, kThreads>(d, t, rows, nrows, nt, o_grad, scr,
                                 [&](const int4& rw, int k, float4& x, float4& v, float4& f) {
                                     const int ti = rw.w + k;
                                     x = sp[rw.x + k];

@@ -1,15 +1,19 @@
 // dpd_server.cpp -- continuous-batching request server over the box and batch
-// API of include/dpd.h (it uses nothing below that API).
+// API of include/dpd.h, plus the few non-synchronising runtime calls of
+// dpd_runtime.hpp.
 //
 // Requests are admitted in arrival order by HBM footprint: each needs
 // dpd_workspace_bytes of its geometry, carved first-fit out of one
 // caller-owned device pool, plus a slot.  Admitted requests keep their state
 // resident; every pump runs one quantum of steps for all active requests as
-// one batch (one launch per kernel for all of them), retires the ones that
-// finished (results copied to host memory, pool block freed) and admits
-// queued requests into the freed memory and slots.  A request's result is
-// the same bits whether it ran alone or in a mix: the batch computes every
-// box exactly as it would alone.
+// one batch (one launch per kernel for all of them) on the server stream.
+// The host does not wait for that quantum: requests that finish with it have
+// their results copied to pinned host memory behind it on the same stream,
+// and a later pump, once those copies are done, completes them and frees
+// their memory; meanwhile new requests are set up on a second stream.  At
+// most two quanta are in flight.  A request's result is the same bits whether
+// it ran alone or in a mix: the batch computes every box exactly as it would
+// alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +31,7 @@
 
 #include "dpd.h"
 #include "dpd_internal.hpp"
+#include "dpd_runtime.hpp"
 #include "pool_alloc.hpp"
 
 namespace {
@@ -52,6 +57,40 @@ int pass(int rc, const char* where)
 using dpd::align256;
 using dpd::PoolAlloc;
 
+// Pinned host blocks for results, reused by size (best fit).
+struct PinnedPool {
+    std::multimap<size_t, char*> free;
+    std::vector<std::pair<char*, size_t>> all;
+
+    char* take(size_t bytes)
+    {
+        auto it = free.lower_bound(bytes);
+        if (it != free.end() && it->first <= 2 * bytes + (1u << 20)) {
+            char* p = it->second;
+            free.erase(it);
+            return p;
+        }
+        char* p = nullptr;
+        if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        all.emplace_back(p, bytes);
+        return p;
+    }
+    void give(char* p)
+    {
+        for (const auto& a : all)
+            if (a.first == p) {
+                free.emplace(a.second, p);
+                return;
+            }
+    }
+    void release()
+    {
+        for (const auto& a : all) (void)hipHostFree(a.first);
+        all.clear();
+        free.clear();
+    }
+};
+
 struct Req {
     uint64_t ticket = 0;
     dpd_geom geom{};
@@ -67,8 +106,20 @@ struct Req {
     int64_t done_steps = 0;
     int32_t status = DPD_EAGAIN;
     dpd_stats stats{};
-    std::vector<float> out_pos, out_vel;  // final state, id order
+    // final state (id order) and device statistics, copied to pinned host
+    // memory behind the request's last quantum
+    char* out = nullptr;
+    float* out_pos = nullptr;
+    float* out_vel = nullptr;
+    dpd::DevStats* out_stats = nullptr;
     double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+// Requests whose last quantum has been enqueued, with the event that passes
+// when their result copies are done.
+struct Retiring {
+    hipEvent_t done = nullptr;
+    std::vector<Req*> reqs;
 };
 
 }  // namespace
@@ -77,11 +128,19 @@ struct dpd_server_s {
     char* pool = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // the caller's: quanta and result copies
+    hipStream_t admin = nullptr;        // setting up admitted requests
     PoolAlloc alloc;
     size_t batch_off = 0, batch_bytes = 0;       // batch tables, reserved at the pool start
     std::deque<Req*> queue;
     std::vector<Req*> active;
+    std::deque<Retiring> retiring;
+    int n_retiring = 0;
+    std::vector<hipEvent_t> spare_events;
+    hipEvent_t quantum_done[2] = {nullptr, nullptr};
+    bool quantum_used[2] = {false, false};
+    int quantum_next = 0;
+    PinnedPool pinned;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
     dpd_batch batch = nullptr;
@@ -96,27 +155,20 @@ struct dpd_server_s {
 
 namespace {
 
-int retire(dpd_server_s* s, Req* r, int status)
+hipEvent_t take_event(dpd_server_s* s)
 {
-    r->status = status;
-    r->t_done = s->now();
-    if (r->box) {
-        const int64_t n = r->geom.n;
-        if (status == DPD_OK || status == DPD_ENONFINITE) {
-            r->out_pos.resize((size_t)n * 3);
-            r->out_vel.resize((size_t)n * 3);
-            int rc = dpd_get_stats(r->box, &r->stats);
-            if (rc != DPD_OK && rc != DPD_ENONFINITE) r->status = rc;
-            if (rc == DPD_ENONFINITE) r->status = rc;
-            if (n > 0) {
-                if (dpd_read(r->box, DPD_POS, r->out_pos.data(), DPD_HOST) != DPD_OK ||
-                    dpd_read(r->box, DPD_VEL, r->out_vel.data(), DPD_HOST) != DPD_OK)
-                    r->status = DPD_EDEVICE;
-            }
-        }
-        dpd_destroy(r->box);
-        r->box = nullptr;
+    if (!s->spare_events.empty()) {
+        hipEvent_t e = s->spare_events.back();
+        s->spare_events.pop_back();
+        return e;
     }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void free_block(dpd_server_s* s, Req* r)
+{
     if (r->has_block) {
         s->alloc.release(r->off, r->bytes);
         r->has_block = false;
@@ -125,14 +177,70 @@ int retire(dpd_server_s* s, Req* r, int status)
     r->pos.shrink_to_fit();
     r->vel.clear();
     r->vel.shrink_to_fit();
+}
+
+// Retire a request that never ran or failed (no copies in flight): destroy
+// its box and free its memory at once.
+int retire_now(dpd_server_s* s, Req* r, int status)
+{
+    r->status = status;
+    r->t_done = s->now();
+    if (r->box) {
+        dpd_destroy(r->box);
+        r->box = nullptr;
+    }
+    free_block(s, r);
     return DPD_OK;
 }
 
-// Create the request's box in its pool block and load its state.
+// Queue the result copies of a request whose last quantum was just enqueued.
+int retire_enqueue(dpd_server_s* s, Req* r, Retiring& grp)
+{
+    const size_t n3 = (size_t)r->geom.n * 3;
+    const size_t state_bytes = (n3 * sizeof(float) + 255) & ~(size_t)255;
+    r->out = s->pinned.take(2 * state_bytes + sizeof(dpd::DevStats));
+    if (!r->out) return sfail(DPD_ENOMEM, "dpd_server: pinned host allocation failed");
+    r->out_pos = (float*)r->out;
+    r->out_vel = (float*)(r->out + state_bytes);
+    r->out_stats = (dpd::DevStats*)(r->out + 2 * state_bytes);
+    const int rc = dpd::box_enqueue_results(r->box, r->out_pos, r->out_vel, r->out_stats);
+    if (rc) return pass(rc, "dpd_server: results");
+    grp.reqs.push_back(r);
+    return DPD_OK;
+}
+
+// Complete the retiring groups whose copies are done (all of them when
+// `wait`): statistics, status, completion time; the box and its memory are
+// released.  Groups complete in order.
+int reap(dpd_server_s* s, bool wait)
+{
+    while (!s->retiring.empty()) {
+        Retiring& g = s->retiring.front();
+        const hipError_t e = wait ? hipEventSynchronize(g.done) : hipEventQuery(g.done);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) return sfail(DPD_EDEVICE, "dpd_server: %s", hipGetErrorString(e));
+        const double t = s->now();
+        for (Req* r : g.reqs) {
+            dpd::stats_from_device(*r->out_stats, &r->stats);
+            r->status = r->stats.nonfinite ? DPD_ENONFINITE : DPD_OK;
+            r->t_done = t;
+            dpd::box_release(r->box);      // its last work is behind the event
+            r->box = nullptr;
+            free_block(s, r);
+        }
+        s->n_retiring -= (int)g.reqs.size();
+        s->spare_events.push_back(g.done);
+        s->retiring.pop_front();
+    }
+    return DPD_OK;
+}
+
+// Create the request's box in its pool block and load its state, on the
+// setup stream; then later work of the box goes to the server stream.
 int materialise(dpd_server_s* s, Req* r)
 {
     dpd_box b = nullptr;
-    int rc = dpd_create(&r->geom, s->pool + r->off, r->bytes, (void*)s->stream, &b);
+    int rc = dpd_create(&r->geom, s->pool + r->off, r->bytes, (void*)s->admin, &b);
     if (rc) return pass(rc, "dpd_server: create");
     r->box = b;
     if ((rc = dpd_set_params(b, &r->params)) || (rc = dpd_set_seed(b, r->seed))) return pass(rc, "dpd_server: setup");
@@ -142,12 +250,13 @@ int materialise(dpd_server_s* s, Req* r)
     else
         rc = dpd_init_random(b, r->init_kT, r->init_seed);
     if (rc) return pass(rc, "dpd_server: state");
-    return DPD_OK;
+    // the setup calls above have synchronised the setup stream
+    return dpd::box_set_stream(b, s->stream);
 }
 
 void admit(dpd_server_s* s)
 {
-    while (!s->queue.empty() && (int)s->active.size() < s->max_slots) {
+    while (!s->queue.empty() && (int)s->active.size() + s->n_retiring < s->max_slots) {
         Req* r = s->queue.front();
         size_t off = 0;
         if (!s->alloc.alloc(r->bytes, &off)) break;          // arrival order: wait for memory
@@ -157,11 +266,11 @@ void admit(dpd_server_s* s)
         r->t_admit = s->now();
         const int rc = materialise(s, r);
         if (rc != DPD_OK) {
-            retire(s, r, rc);
+            retire_now(s, r, rc);
             continue;
         }
         if (r->nsteps == 0) {
-            retire(s, r, DPD_OK);
+            retire_now(s, r, DPD_OK);
             continue;
         }
         s->active.push_back(r);
@@ -185,6 +294,15 @@ int dpd_server_create(void* dev_pool, size_t pool_bytes, int32_t max_slots, void
     if (pool_bytes <= tb) return sfail(DPD_ENOMEM, "dpd_server_create: pool smaller than the batch tables");
     dpd_server_s* s = new (std::nothrow) dpd_server_s();
     if (!s) return sfail(DPD_ENOMEM, "dpd_server_create: host allocation failed");
+    hipError_t e = hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->quantum_done[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (hipEvent_t q : s->quantum_done)
+            if (q) (void)hipEventDestroy(q);
+        if (s->admin) (void)hipStreamDestroy(s->admin);
+        delete s;
+        return sfail(DPD_EDEVICE, "dpd_server_create: %s", hipGetErrorString(e));
+    }
     s->pool = (char*)dev_pool;
     s->pool_bytes = pool_bytes;
     s->max_slots = max_slots;
@@ -233,38 +351,59 @@ int dpd_server_pump(dpd_server s, int32_t quantum_steps, int32_t* ran_steps)
     if (!s) return sfail(DPD_EINVAL, "dpd_server_pump: null server");
     if (quantum_steps < 1) return sfail(DPD_EINVAL, "dpd_server_pump: quantum_steps < 1");
     if (ran_steps) *ran_steps = 0;
+    int rc = reap(s, false);
+    if (rc) return rc;
     admit(s);
-    if (s->active.empty()) return DPD_OK;
+    if (s->active.empty()) return reap(s, s->queue.empty());   // nothing to run: let the last copies finish
     // a quantum never runs a request past its end
     int64_t q = quantum_steps;
     for (Req* r : s->active) q = std::min(q, r->nsteps - r->done_steps);
     if (s->members_changed || !s->batch) {
-        if (s->batch) dpd_batch_destroy(s->batch);
-        s->batch = nullptr;
         std::vector<dpd_box> boxes;
         for (Req* r : s->active) boxes.push_back(r->box);
-        int rc = dpd_batch_create(boxes.data(), (int32_t)boxes.size(), s->pool + s->batch_off, s->batch_bytes,
+        if (!s->batch)
+            rc = dpd_batch_create(boxes.data(), (int32_t)boxes.size(), s->pool + s->batch_off, s->batch_bytes,
                                   (void*)s->stream, &s->batch);
+        else
+            rc = dpd::batch_set_boxes(s->batch, boxes.data(), (int32_t)boxes.size());
         if (rc) return pass(rc, "dpd_server_pump: batch");
         s->members_changed = false;
     }
-    int rc = dpd_batch_step(s->batch, q);
+    rc = dpd_batch_step(s->batch, q);
     if (rc) return pass(rc, "dpd_server_pump: step");
     if (ran_steps) *ran_steps = (int32_t)q;
+    // requests that end with this quantum: their results are copied out
+    // behind it, and a later pump completes them
+    Retiring grp;
     std::vector<Req*> still;
     for (Req* r : s->active) {
         r->done_steps += q;
         s->steps_run += q * r->geom.n;
-        if (r->done_steps >= r->nsteps) {
-            retire(s, r, DPD_OK);
-            s->members_changed = true;
-        } else {
+        if (r->done_steps < r->nsteps) {
             still.push_back(r);
+            continue;
         }
+        rc = retire_enqueue(s, r, grp);
+        if (rc) return rc;
     }
     s->active.swap(still);
-    if (s->members_changed) admit(s);
-    return DPD_OK;
+    if (!grp.reqs.empty()) {
+        grp.done = take_event(s);
+        if (!grp.done) return sfail(DPD_EDEVICE, "dpd_server_pump: event creation failed");
+        if (hipEventRecord(grp.done, s->stream) != hipSuccess) return sfail(DPD_EDEVICE, "dpd_server_pump: event record");
+        s->n_retiring += (int)grp.reqs.size();
+        s->retiring.push_back(std::move(grp));
+        s->members_changed = true;
+    }
+    // at most two quanta in flight: wait for the one before this
+    const int k = s->quantum_next;
+    s->quantum_next ^= 1;
+    if (hipEventRecord(s->quantum_done[k], s->stream) != hipSuccess)
+        return sfail(DPD_EDEVICE, "dpd_server_pump: event record");
+    s->quantum_used[k] = true;
+    if (s->quantum_used[k ^ 1] && hipEventSynchronize(s->quantum_done[k ^ 1]) != hipSuccess)
+        return sfail(DPD_EDEVICE, "dpd_server_pump: quantum failed");
+    return reap(s, false);
 }
 
 int dpd_server_poll(dpd_server s, uint64_t ticket, dpd_result* res, float* pos_n3, float* vel_n3)
@@ -273,15 +412,24 @@ int dpd_server_poll(dpd_server s, uint64_t ticket, dpd_result* res, float* pos_n
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return sfail(DPD_ENOTFOUND, "dpd_server_poll: unknown ticket %llu", (unsigned long long)ticket);
     Req* r = it->second.get();
-    if (r->status == DPD_EAGAIN) return DPD_EAGAIN;
+    if (r->status == DPD_EAGAIN) {
+        const int rc = reap(s, false);
+        if (rc) return rc;
+        if (r->status == DPD_EAGAIN) return DPD_EAGAIN;
+    }
     std::memset(res, 0, sizeof *res);
     res->stats = r->stats;
     res->status = r->status;
     res->t_submit = r->t_submit;
     res->t_admit = r->t_admit;
     res->t_done = r->t_done;
-    if (pos_n3 && !r->out_pos.empty()) std::memcpy(pos_n3, r->out_pos.data(), r->out_pos.size() * sizeof(float));
-    if (vel_n3 && !r->out_vel.empty()) std::memcpy(vel_n3, r->out_vel.data(), r->out_vel.size() * sizeof(float));
+    const size_t bytes = (size_t)r->geom.n * 3 * sizeof(float);
+    if (r->out) {
+        if (pos_n3 && bytes) std::memcpy(pos_n3, r->out_pos, bytes);
+        if (vel_n3 && bytes) std::memcpy(vel_n3, r->out_vel, bytes);
+        s->pinned.give(r->out);
+        r->out = nullptr;
+    }
     s->reqs.erase(it);
     return DPD_OK;
 }
@@ -290,7 +438,7 @@ int dpd_server_counts(dpd_server s, int32_t* queued, int32_t* active, int64_t* p
 {
     if (!s) return sfail(DPD_EINVAL, "dpd_server_counts: null server");
     if (queued) *queued = (int32_t)s->queue.size();
-    if (active) *active = (int32_t)s->active.size();
+    if (active) *active = (int32_t)s->active.size() + s->n_retiring;
     if (particle_steps) *particle_steps = s->steps_run;
     return DPD_OK;
 }
@@ -300,10 +448,22 @@ double dpd_server_clock(dpd_server s) { return s ? s->now() : 0.0; }
 int dpd_server_destroy(dpd_server s)
 {
     if (!s) return DPD_OK;
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->admin);
+    (void)reap(s, true);
     if (s->batch) dpd_batch_destroy(s->batch);
     for (Req* r : s->active)
-        if (r->box) dpd_destroy(r->box);
-    (void)hipStreamSynchronize(s->stream);
+        if (r->box) dpd::box_release(r->box);
+    for (Retiring& g : s->retiring) {
+        for (Req* r : g.reqs)
+            if (r->box) dpd::box_release(r->box);
+        (void)hipEventDestroy(g.done);
+    }
+    for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->quantum_done)
+        if (e) (void)hipEventDestroy(e);
+    s->pinned.release();
+    (void)hipStreamDestroy(s->admin);
     delete s;
     return DPD_OK;
 }
