@@ -474,7 +474,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cube48_rho3")
-    ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage with HIP events")
+    ap.add_argument("--profile-steps", type=int, default=50, help="eager steps timed per stage (kernel-recorded HIP events)")
     ap.add_argument("--force-reps", type=int, default=20, help="force-kernel launches timed back to back")
     ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -543,9 +543,10 @@ def main():
         sys.exit(1)
     value = n * args.steps / (ms / 1e3)
 
-    # per-stage device time (HIP events around each stage of eager steps on
-    # the box stream); the force stage is the step's force kernel, which also
-    # integrates (kick-drift fused into its write-out)
+    # per-stage device time of eager steps on the box stream, from events that
+    # each stage's first kernel records as it starts and its last as it ends
+    # (the kernels' own time); the force stage is the step's force kernel,
+    # which also integrates (kick-drift fused into its write-out)
     stage = box.profile_steps(args.profile_steps)
     f_ms = stage["force"]
     # the same kernel without the fused kick-drift, launched back to back

@@ -352,12 +352,16 @@ int dpd_reset_accumulators(dpd_box box);
 /* Destroy a box (NULL-safe).  Synchronises; the workspace may be freed after. */
 int dpd_destroy(dpd_box box);
 
-/* Run nsteps >= 1 steps eagerly (no graph) with a HIP event pair around
- * each stage on the box stream, and return the mean device time per step of
- * each stage in ms_out[4]: binning (scan, scatter, gather),
- * pair forces, virial (0 unless DPD_FLAG_VIRIAL), integrate (the fold of the
- * reductions, which a graph runs inside the next step's scan, runs after the
- * timed stages).  The steps advance the box like dpd_step.  Synchronises. */
+/* Run nsteps >= 1 steps eagerly (no graph) and return the mean device time
+ * per step of each stage in ms_out[4]: binning (scan, scatter, gather),
+ * pair forces (with the kick-drift when it is fused into the force kernel:
+ * boxes without walls), virial (0 unless DPD_FLAG_VIRIAL), integrate (0 when
+ * fused).  Each stage is timed by events that its first kernel records as it
+ * starts and its last as it ends (hipExtLaunchKernel), so the times are the
+ * kernels' own, from the first one's start to the last one's end.  The fold
+ * of the reductions, which a graph runs inside the next step's scan, runs
+ * after the timed stages.  The steps advance the box like dpd_step.
+ * Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
 
 /* ---- a run that allocates nothing -------------------------------------------
@@ -444,11 +448,15 @@ int dpd_batch_destroy(dpd_batch batch);
  * A request server over one caller-owned device pool.  Requests are admitted
  * in arrival order when a slot is free and their footprint
  * (dpd_workspace_bytes) fits in the pool; admitted requests keep their state
- * resident; each pump runs one quantum of steps for all active requests as
- * one batch, retires finished ones (results copied to host memory, memory
- * freed) and admits waiting requests, so requests that arrive while others
- * run join the next quantum.  A request's result is the same bits alone or in
- * a mix.  A request is one species without frozen particles: its params may
+ * resident; each pump queues one quantum of steps for all active requests,
+ * as one batch per density class (rho <= 4.5 and above, each at its own
+ * launch shape), on the server stream without waiting for it; requests that
+ * finish with a quantum have their results copied to pinned host memory
+ * behind it and are completed (memory freed) by a later pump or poll once
+ * those copies are done; waiting requests are admitted (set up on a second
+ * stream of the server's own) as slots and memory free up, so requests that
+ * arrive while others run join the next quantum.  At most two quanta are in
+ * flight.  A request's result is the same bits alone or in a mix.  A request is one species without frozen particles: its params may
  * name a wall (fluid particles then bounce off the SDF surface) but carry no
  * frozen layer; species and frozen layers need a box of one's own. */
 typedef struct dpd_server_s* dpd_server;
@@ -479,9 +487,12 @@ int dpd_server_create(void* dev_pool, size_t pool_bytes, int32_t max_slots, void
 /* Queue a request (never blocks; DPD_ENOMEM if it could never fit). */
 int dpd_server_submit(dpd_server server, const dpd_request* req, uint64_t* ticket);
 
-/* Admit, run one quantum of up to quantum_steps steps for all active requests
- * (never past a request's end), retire finished ones, admit again.
- * *ran_steps (may be NULL) receives the steps run.  Synchronises. */
+/* Complete requests whose result copies are done, admit, queue one quantum
+ * of up to quantum_steps steps for all active requests (never past a
+ * request's end) and the result copies of those it finishes.  *ran_steps
+ * (may be NULL) receives the steps queued.  Waits only for the quantum
+ * queued by the previous pump (at most two in flight), or, with no request
+ * active or waiting, for the last result copies. */
 int dpd_server_pump(dpd_server server, int32_t quantum_steps, int32_t* ran_steps);
 
 /* DPD_EAGAIN until the request is done; then fills the result and, if not

@@ -73,7 +73,8 @@ constexpr size_t kLdsLimit = 160 * 1024 - 1280;  // LDS per CU less the kernels'
 // Tile shapes the autotuners try (cells per edge).
 constexpr int kTuneCand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 4, 2}, {6, 3, 3}, {4, 4, 2}, {4, 2, 2}, {2, 2, 4},
                                 {4, 2, 4}, {2, 4, 4}, {3, 3, 3}, {6, 4, 4}, {2, 2, 2}, {8, 2, 2}, {6, 6, 4},
-                                {8, 8, 4}, {3, 3, 2}, {8, 3, 3}, {6, 4, 2}, {6, 2, 2}};
+                                {8, 8, 4}, {3, 3, 2}, {8, 3, 3}, {6, 4, 2}, {6, 2, 2}, {6, 6, 3}, {6, 6, 6},
+                                {8, 6, 4}, {12, 4, 4}, {12, 6, 4}, {8, 8, 2}, {6, 6, 2}, {12, 3, 3}};
 
 }  // namespace
 
@@ -309,29 +310,47 @@ dpd::StepConst step_const(const dpd_box_s* b)
     return sc;
 }
 
-// Default cell tile of the LDS force kernel (measured on MI355X): 4x4x4
-// cells at solvent densities up to 4.5, 4x2x2 above.
+// Default cell tile and workgroup size of the LDS force kernel, from
+// sweeps on MI355X.  A box large enough to give at least kBigTiles tiles of
+// the large shape takes it: 6x6x4 cells with 1024 threads at densities up
+// to 4.5 (the 48^3 box at rho = 3 steps in 82.6 us, against 93 us with 4x4x4
+// and 512), 8x4x4 with 1024 above (the 192x96x96 box at rho = 8: 4.99 ms
+// against 5.67 ms with 4x4x4).  Smaller boxes keep more, smaller tiles for
+// parallelism: 4x4x4 (dilute) or 4x2x2 (dense) with 512 threads.  Where a
+// shape's LDS does not fit a CU (denser fluids) the next one of the list that
+// does.
+struct Shape {
+    int t[3];
+    int threads;
+};
+constexpr int kBigTiles = 512;
+constexpr Shape kDiluteShapes[] = {{{6, 6, 4}, 1024}, {{4, 4, 4}, 512}, {{4, 2, 2}, 512}, {{2, 2, 2}, 256}};
+constexpr Shape kDenseShapes[] = {{{8, 4, 4}, 1024}, {{4, 2, 2}, 512}, {{3, 2, 2}, 512}, {{2, 2, 2}, 256}};
+static_assert(sizeof kDiluteShapes == sizeof kDenseShapes, "both lists have four shapes");
+
 dpd::TileConst tile_for(const dpd_box_s* b, const int* req, int threads = 0)
 {
-    if (threads <= 0) threads = b->threads_req > 0 ? b->threads_req : dpd::kForceBlock;
-    int t[3] = {req[0], req[1], req[2]};
+    if (threads <= 0) threads = b->threads_req;     // 0: the default of the shape
     // the tile capacities follow the density of the occupied cells: a box
     // with walls leaves the cells beyond the frozen layers empty
     // (unless that would not fit a CU's LDS, as for a clump of particles:
     // overfull tiles then take the gather path)
     const double rho_mean = b->nc > 0 ? (double)b->n / (double)b->nc : 0.0;
+    dpd::TileConst tc{};
     for (const double rho : {b->rho_occ > 1.1 * rho_mean ? b->rho_occ : rho_mean, rho_mean}) {
-        int u[3] = {t[0], t[1], t[2]};
-        if (u[0] <= 0) {
-            const bool dilute = rho <= 4.5;
-            u[0] = 4;
-            u[1] = dilute ? 4 : 2;
-            u[2] = dilute ? 4 : 2;
+        if (req[0] > 0) {
+            tc = dpd::make_tile_const(b->cells, rho, req, threads > 0 ? threads : dpd::kForceBlock, 0, 0);
+            if ((size_t)tc.lds_bytes <= kLdsLimit) return tc;
+            continue;
         }
-        const dpd::TileConst tc = dpd::make_tile_const(b->cells, rho, u, threads, 0, 0);
-        if ((size_t)tc.lds_bytes <= kLdsLimit || rho == rho_mean) return tc;
+        const Shape* shapes = rho <= 4.5 ? kDiluteShapes : kDenseShapes;
+        for (int k = 0; k < 4; ++k) {
+            tc = dpd::make_tile_const(b->cells, rho, shapes[k].t, threads > 0 ? threads : shapes[k].threads, 0, 0);
+            if (k == 0 && tc.ntiles < kBigTiles) continue;     // a small box: more, smaller tiles
+            if ((size_t)tc.lds_bytes <= kLdsLimit) return tc;
+        }
     }
-    return dpd::TileConst{};   // not reached
+    return tc;   // nothing fits at any capacity: the callers report it
 }
 
 // Rebuild the host descriptor and single-box plan from the box's current
@@ -1059,39 +1078,41 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
     if (!b || !ms_out) return fail(DPD_EINVAL, "dpd_profile_steps: null argument");
     if (nsteps < 1) return fail(DPD_EINVAL, "dpd_profile_steps: nsteps < 1");
     if (!ready(b)) return fail(DPD_ESTATE, "dpd_profile_steps: set params, seed and state first");
-    hipEvent_t ev[5] = {};
-    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    double acc[4] = {0, 0, 0, 0};
+    // one event pair per stage, recorded by the stage's first kernel as it
+    // starts and its last as it ends: the times are the kernels' own
+    hipEvent_t ev[8] = {};
     int rc = DPD_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(DPD_EDEVICE, "dpd_profile_steps: hipEventCreate failed");
+    double acc[4] = {0, 0, 0, 0};
     for (int64_t k = 0; k < nsteps && rc == DPD_OK; ++k) {
-        hipError_t e = hipEventRecord(ev[0], b->stream);
-        if (e == hipSuccess && !b->binned) e = dpd::launch_bin(b->lp, b->stream);
+        const bool bin = !b->binned;
+        hipError_t e = hipSuccess;
+        if (bin) e = dpd::launch_bin(b->lp, b->stream, ev[0], ev[1]);
         b->binned = false;
-        if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
-        if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream, true);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
-        if (e == hipSuccess) e = dpd::launch_virial(b->lp, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
-        if (e == hipSuccess && !b->lp.fuse) e = dpd::launch_integrate(b->lp, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[4], b->stream);
+        if (e == hipSuccess) e = dpd::launch_force(b->lp, b->stream, true, ev[2], ev[3]);
+        const bool vir = b->lp.any_virial && b->lp.total[dpd::kWPart] > 0, integ = !b->lp.fuse;
+        if (e == hipSuccess && vir) e = dpd::launch_virial(b->lp, b->stream, ev[4], ev[5]);
+        if (e == hipSuccess && integ) e = dpd::launch_integrate(b->lp, b->stream, ev[6], ev[7]);
         // the reductions' fold normally rides in the next step's scan: here
         // it runs after the timed stages
         if (e == hipSuccess) e = dpd::launch_fold(b->lp, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
-        for (int s = 0; s < 4 && e == hipSuccess; ++s) {
-            if (s == 2 && !b->lp.any_virial) continue;   // no virial kernel: nothing timed
-            if (s == 3 && b->lp.fuse) continue;          // integrated inside the force kernel
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        const bool timed[4] = {bin, true, vir, integ};
+        for (int st = 0; st < 4 && e == hipSuccess; ++st) {
+            if (!timed[st]) continue;
             float ms = 0.0f;
-            e = hipEventElapsedTime(&ms, ev[s], ev[s + 1]);
-            acc[s] += ms;
+            e = hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]);
+            acc[st] += ms;
         }
         if (e != hipSuccess) rc = fail(DPD_EDEVICE, "dpd_profile_steps: %s", hipGetErrorString(e));
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     b->keys_valid = true;
     b->have_force = true;
-    for (int s = 0; s < 4; ++s) ms_out[s] = acc[s] / (double)nsteps;
+    for (int st = 0; st < 4; ++st) ms_out[st] = acc[st] / (double)nsteps;
     return DPD_OK;
 }
 

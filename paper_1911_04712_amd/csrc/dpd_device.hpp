@@ -157,6 +157,39 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// A double moved by a DPP row shift (kCtrl = row_shr:n) inside rows of 16
+// lanes; lanes whose source lies outside their row get 0.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_row_shr(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum of a double over the 64 lanes of a wave in a fixed order, with no LDS
+// round trips: a tree inside each row of 16 lanes (DPP row shifts by 1, 2, 4
+// and 8, which leave the row's sum in its last lane), then the four row sums
+// as (r0 + r1) + (r2 + r3).  Every lane of the wave must be active; every lane
+// gets the sum.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_row_shr<0x111>(v);
+    v += dpp_row_shr<0x112>(v);
+    v += dpp_row_shr<0x114>(v);
+    v += dpp_row_shr<0x118>(v);
+    return (readlane_f64(v, 15) + readlane_f64(v, 31)) + (readlane_f64(v, 47) + readlane_f64(v, 63));
+}
+
 // Block-wide sum in a fixed order (lane tree inside each wave, then waves in
 // index order).  All threads of the block must call it.
 template <typename T>

@@ -85,14 +85,12 @@ __device__ __forceinline__ bool pair_fx(float4 pi, float4 vi, float4 pj, float4 
     const bool live = r2 > 0.0f && (!kCut || r2 < 1.0f);
     const float Fx = live ? fs * (dx * rinv) : 0.0f, Fy = live ? fs * (dy * rinv) : 0.0f,
                 Fz = live ? fs * (dz * rinv) : 0.0f;
-    if (!(fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit)) {
-        fx = fy = fz = 0;
-        return false;
-    }
-    fx = fx_of(Fx);
-    fy = fx_of(Fy);
-    fz = fx_of(Fz);
-    return true;
+    // out of the fixed-point range (or NaN): adds nothing, reported (selects, not a branch)
+    const bool ok = fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit;
+    fx = fx_of(ok ? Fx : 0.0f);
+    fy = fx_of(ok ? Fy : 0.0f);
+    fz = fx_of(ok ? Fz : 0.0f);
+    return ok;
 }
 
 // Force on particle i (cell order) by gathering over its 27 neighbour cells;
@@ -215,13 +213,16 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
         ia = wa;
         ib = wb;
     }
-    atomicAdd((unsigned long long*)&acc[3 * ia], (unsigned long long)fx);
-    atomicAdd((unsigned long long*)&acc[3 * ia + 1], (unsigned long long)fy);
-    atomicAdd((unsigned long long*)&acc[3 * ia + 2], (unsigned long long)fz);
+    // tile indices are below 2^24: 24-bit multiplies for the LDS offsets
+    unsigned long long* pa = (unsigned long long*)((char*)acc + __umul24((unsigned)ia, 24u));
+    atomicAdd(pa, (unsigned long long)fx);
+    atomicAdd(pa + 1, (unsigned long long)fy);
+    atomicAdd(pa + 2, (unsigned long long)fz);
     if (ib >= 0) {                       // both ends in the tile: apply the reaction too
-        atomicAdd((unsigned long long*)&acc[3 * ib], (unsigned long long)(-fx));
-        atomicAdd((unsigned long long*)&acc[3 * ib + 1], (unsigned long long)(-fy));
-        atomicAdd((unsigned long long*)&acc[3 * ib + 2], (unsigned long long)(-fz));
+        unsigned long long* pb = (unsigned long long*)((char*)acc + __umul24((unsigned)ib, 24u));
+        atomicAdd(pb, (unsigned long long)(-fx));
+        atomicAdd(pb + 1, (unsigned long long)(-fy));
+        atomicAdd(pb + 2, (unsigned long long)(-fz));
     }
 }
 
@@ -731,36 +732,34 @@ TileConst make_tile_const(const int* cells, double rho, const int* tile, int thr
 }
 
 template <bool kSp, bool kFuse>
-static void launch_tiled(const LaunchPlan& lp, hipStream_t s)
+static void launch_tiled(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     const dim3 grid(lp.total[kWTile]);
     switch (lp.force_threads) {
     case 256:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 256, kFuse>), grid, dim3(256), lp.lds_force, s, lp.desc, lp.pre,
-                           lp.nbox);
+        launch_timed(k_force_tiled<kSp, 256, kFuse>, grid, dim3(256), lp.lds_force, s, t0, t1, lp.desc, lp.pre, lp.nbox);
         break;
     case 1024:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 1024, kFuse>), grid, dim3(1024), lp.lds_force, s, lp.desc, lp.pre,
-                           lp.nbox);
+        launch_timed(k_force_tiled<kSp, 1024, kFuse>, grid, dim3(1024), lp.lds_force, s, t0, t1, lp.desc, lp.pre,
+                     lp.nbox);
         break;
     default:
-        hipLaunchKernelGGL((k_force_tiled<kSp, 512, kFuse>), grid, dim3(512), lp.lds_force, s, lp.desc, lp.pre,
-                           lp.nbox);
+        launch_timed(k_force_tiled<kSp, 512, kFuse>, grid, dim3(512), lp.lds_force, s, t0, t1, lp.desc, lp.pre, lp.nbox);
         break;
     }
 }
 
-hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate)
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate, hipEvent_t t0, hipEvent_t t1)
 {
     if (lp.reference_force) {
         if (lp.total[kWPart] > 0)
-            hipLaunchKernelGGL(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+            launch_timed(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, t0, t1, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
         const bool fuse = integrate && lp.fuse;
         if (lp.species)
-            fuse ? launch_tiled<true, true>(lp, s) : launch_tiled<true, false>(lp, s);
+            fuse ? launch_tiled<true, true>(lp, s, t0, t1) : launch_tiled<true, false>(lp, s, t0, t1);
         else
-            fuse ? launch_tiled<false, true>(lp, s) : launch_tiled<false, false>(lp, s);
+            fuse ? launch_tiled<false, true>(lp, s, t0, t1) : launch_tiled<false, false>(lp, s, t0, t1);
     }
     return hipGetLastError();
 }

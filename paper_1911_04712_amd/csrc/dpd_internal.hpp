@@ -1,5 +1,6 @@
 // dpd_internal.hpp -- data layout shared by the host runtime and the kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -230,12 +231,29 @@ hipError_t launch_set_frozen(const float4* pos, float4* vel, int n, const unsign
                              const StepConst& sc, hipStream_t s);
 hipError_t launch_get_frozen(const float4* pos, const float4* vel, int n, unsigned char* frozen_by_id, hipStream_t s);
 hipError_t launch_wall_sdf(const float4* pos, int n, const StepConst& sc, float* sdf_by_id, hipStream_t s);
-hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s);
+// Stage launchers.  t0 / t1 (optional): events that the first kernel of the
+// stage records as it starts and the last as it ends (hipExtLaunchKernel), so
+// that the events time the stage's kernels alone; null in normal steps and
+// in captured graphs.
+hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // integrate: a step's force launch, which also integrates when lp.fuse (the
 // tuners and timers pass false: forces only, the state is left alone)
-hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate);
-hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s);
-hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s);
+hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
+hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+
+// A kernel launch that records t0 when it starts and t1 when it ends (either
+// may be null; both null is a plain launch).
+template <typename K, typename... A>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, unsigned lds, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
+                         A... args)
+{
+    if (t0 || t1)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, s, t0, t1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
 hipError_t launch_fold(const LaunchPlan& lp, hipStream_t s);
 // rho: particles per occupied cell (the density the tile capacities are sized for)
 TileConst make_tile_const(const int* cells, double rho, const int* tile, int threads, int smax_override,

@@ -423,13 +423,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
     d.vel_b[s + rank] = v;
 }
 
-hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s)
+hipError_t launch_bin(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
+    const bool parts = lp.total[kWPart] > 0;
     if (lp.total[kWChunk] > 0)
-        hipLaunchKernelGGL(k_scan, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
-    if (lp.total[kWPart] > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
-        hipLaunchKernelGGL(k_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+        launch_timed(k_scan, dim3(lp.total[kWChunk]), dim3(kBlock), 0, s, t0, parts ? nullptr : t1, lp.desc, lp.pre,
+                     lp.nbox);
+    if (parts) {
+        launch_timed(k_scatter, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.total[kWChunk] > 0 ? nullptr : t0,
+                     nullptr, lp.desc, lp.pre, lp.nbox);
+        launch_timed(k_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, nullptr, t1, lp.desc, lp.pre, lp.nbox);
     }
     return hipGetLastError();
 }
@@ -493,10 +496,10 @@ __global__ __launch_bounds__(kBlock) void k_virial(const BoxDesc* __restrict__ d
     if (threadIdx.x == 0 && v != 0) atomicAdd((unsigned long long*)&d.st->virial_fx, (unsigned long long)v);
 }
 
-hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s)
+hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     if (!lp.any_virial || lp.total[kWPart] <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_virial, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+    launch_timed(k_virial, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, t0, t1, lp.desc, lp.pre, lp.nbox);
     return hipGetLastError();
 }
 
@@ -752,12 +755,12 @@ __global__ __launch_bounds__(kBlock) void k_fold_stats(const BoxDesc* __restrict
     fold_stats(desc[blockIdx.x]);
 }
 
-hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s)
+hipError_t launch_integrate(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     if (lp.walls)
-        hipLaunchKernelGGL(k_integrate<true>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+        launch_timed(k_integrate<true>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, t0, t1, lp.desc, lp.pre, lp.nbox);
     else
-        hipLaunchKernelGGL(k_integrate<false>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, lp.desc, lp.pre, lp.nbox);
+        launch_timed(k_integrate<false>, dim3(lp.total[kWInt]), dim3(kBlock), 0, s, t0, t1, lp.desc, lp.pre, lp.nbox);
     return hipGetLastError();
 }
 

@@ -6,7 +6,8 @@
 // dpd_workspace_bytes of its geometry, carved first-fit out of one
 // caller-owned device pool, plus a slot.  Admitted requests keep their state
 // resident; every pump runs one quantum of steps for all active requests as
-// one batch (one launch per kernel for all of them) on the server stream.
+// one batch per density class (one launch per kernel for all requests of
+// a class, each class at its own launch shape) on the server stream.
 // The host does not wait for that quantum: requests that finish with it have
 // their results copied to pinned host memory behind it on the same stream,
 // and a later pump, once those copies are done, completes them and frees
@@ -128,10 +129,11 @@ struct dpd_server_s {
     char* pool = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 0;
+    static constexpr int kClasses = 2;  // dilute (rho <= 4.5) and dense fluids: each its own batch
     hipStream_t stream = nullptr;       // the caller's: quanta and result copies
     hipStream_t admin = nullptr;        // setting up admitted requests
     PoolAlloc alloc;
-    size_t batch_off = 0, batch_bytes = 0;       // batch tables, reserved at the pool start
+    size_t batch_off[kClasses] = {0, 0}, batch_bytes = 0;   // batch tables, reserved at the pool start
     std::deque<Req*> queue;
     std::vector<Req*> active;
     std::deque<Retiring> retiring;
@@ -143,7 +145,7 @@ struct dpd_server_s {
     PinnedPool pinned;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
-    dpd_batch batch = nullptr;
+    dpd_batch batch[kClasses] = {nullptr, nullptr};
     bool members_changed = true;
     std::chrono::steady_clock::time_point t0;
     int64_t steps_run = 0;                        // particle-steps completed
@@ -235,6 +237,14 @@ int reap(dpd_server_s* s, bool wait)
     return DPD_OK;
 }
 
+// Density class of a request: the default launch shapes differ at rho 4.5
+// (one launch has one shape, so the two classes are batched apart).
+int density_class(const Req* r)
+{
+    const double nc = (double)r->geom.cells[0] * r->geom.cells[1] * r->geom.cells[2];
+    return (double)r->geom.n / nc <= 4.5 ? 0 : 1;
+}
+
 // Create the request's box in its pool block and load its state, on the
 // setup stream; then later work of the box goes to the server stream.
 int materialise(dpd_server_s* s, Req* r)
@@ -244,6 +254,15 @@ int materialise(dpd_server_s* s, Req* r)
     if (rc) return pass(rc, "dpd_server: create");
     r->box = b;
     if ((rc = dpd_set_params(b, &r->params)) || (rc = dpd_set_seed(b, r->seed))) return pass(rc, "dpd_server: setup");
+    // every box of a class batch at one launch shape: the small-box default
+    // of its density class (a large box alone would take a larger tile, whose
+    // LDS reservation the whole batch would then carry)
+    // (a fluid too dense for that shape's LDS keeps the box's own default)
+    static const int32_t kTile[dpd_server_s::kClasses][3] = {{4, 4, 4}, {4, 2, 2}};
+    if (dpd_set_force_threads(b, 512) != DPD_OK || dpd_set_tile(b, kTile[density_class(r)]) != DPD_OK) {
+        static const int32_t kDefault[3] = {0, 0, 0};
+        if ((rc = dpd_set_force_threads(b, 0)) || (rc = dpd_set_tile(b, kDefault))) return pass(rc, "dpd_server: tile");
+    }
     if (!r->pos.empty() || r->geom.n == 0)
         rc = dpd_set_state(b, r->pos.empty() ? nullptr : r->pos.data(), r->vel.empty() ? nullptr : r->vel.data(),
                            DPD_HOST);
@@ -291,7 +310,8 @@ int dpd_server_create(void* dev_pool, size_t pool_bytes, int32_t max_slots, void
     size_t tb = 0;
     if (dpd_batch_workspace_bytes(max_slots, &tb)) return pass(DPD_EINVAL, "dpd_server_create");
     tb = align256(tb);
-    if (pool_bytes <= tb) return sfail(DPD_ENOMEM, "dpd_server_create: pool smaller than the batch tables");
+    if (pool_bytes <= dpd_server_s::kClasses * tb)
+        return sfail(DPD_ENOMEM, "dpd_server_create: pool smaller than the batch tables");
     dpd_server_s* s = new (std::nothrow) dpd_server_s();
     if (!s) return sfail(DPD_ENOMEM, "dpd_server_create: host allocation failed");
     hipError_t e = hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking);
@@ -308,7 +328,7 @@ int dpd_server_create(void* dev_pool, size_t pool_bytes, int32_t max_slots, void
     s->max_slots = max_slots;
     s->stream = (hipStream_t)hip_stream;
     s->alloc.reset(pool_bytes);
-    s->alloc.alloc(tb, &s->batch_off);
+    for (int c = 0; c < dpd_server_s::kClasses; ++c) s->alloc.alloc(tb, &s->batch_off[c]);
     s->batch_bytes = tb;
     s->t0 = std::chrono::steady_clock::now();
     *out = s;
@@ -321,7 +341,7 @@ int dpd_server_submit(dpd_server s, const dpd_request* q, uint64_t* ticket)
     size_t bytes = 0;
     if (dpd_workspace_bytes(&q->geom, &bytes)) return pass(DPD_EINVAL, "dpd_server_submit: geometry");
     if (q->nsteps < 0) return sfail(DPD_EINVAL, "dpd_server_submit: nsteps < 0");
-    if (align256(bytes) > s->pool_bytes - s->batch_bytes)
+    if (align256(bytes) > s->pool_bytes - dpd_server_s::kClasses * s->batch_bytes)
         return sfail(DPD_ENOMEM, "dpd_server_submit: request needs %zu bytes, more than the whole pool", bytes);
     if ((q->pos_n3 == nullptr) != (q->vel_n3 == nullptr))
         return sfail(DPD_EINVAL, "dpd_server_submit: give both pos and vel, or neither");
@@ -358,19 +378,22 @@ int dpd_server_pump(dpd_server s, int32_t quantum_steps, int32_t* ran_steps)
     // a quantum never runs a request past its end
     int64_t q = quantum_steps;
     for (Req* r : s->active) q = std::min(q, r->nsteps - r->done_steps);
-    if (s->members_changed || !s->batch) {
-        std::vector<dpd_box> boxes;
-        for (Req* r : s->active) boxes.push_back(r->box);
-        if (!s->batch)
-            rc = dpd_batch_create(boxes.data(), (int32_t)boxes.size(), s->pool + s->batch_off, s->batch_bytes,
-                                  (void*)s->stream, &s->batch);
-        else
-            rc = dpd::batch_set_boxes(s->batch, boxes.data(), (int32_t)boxes.size());
-        if (rc) return pass(rc, "dpd_server_pump: batch");
-        s->members_changed = false;
+    std::vector<dpd_box> boxes[dpd_server_s::kClasses];
+    for (Req* r : s->active) boxes[density_class(r)].push_back(r->box);
+    for (int c = 0; c < dpd_server_s::kClasses; ++c) {
+        if (boxes[c].empty()) continue;
+        if (s->members_changed || !s->batch[c]) {
+            if (!s->batch[c])
+                rc = dpd_batch_create(boxes[c].data(), (int32_t)boxes[c].size(), s->pool + s->batch_off[c],
+                                      s->batch_bytes, (void*)s->stream, &s->batch[c]);
+            else
+                rc = dpd::batch_set_boxes(s->batch[c], boxes[c].data(), (int32_t)boxes[c].size());
+            if (rc) return pass(rc, "dpd_server_pump: batch");
+        }
+        rc = dpd_batch_step(s->batch[c], q);
+        if (rc) return pass(rc, "dpd_server_pump: step");
     }
-    rc = dpd_batch_step(s->batch, q);
-    if (rc) return pass(rc, "dpd_server_pump: step");
+    s->members_changed = false;
     if (ran_steps) *ran_steps = (int32_t)q;
     // requests that end with this quantum: their results are copied out
     // behind it, and a later pump completes them
@@ -451,7 +474,8 @@ int dpd_server_destroy(dpd_server s)
     (void)hipStreamSynchronize(s->stream);
     (void)hipStreamSynchronize(s->admin);
     (void)reap(s, true);
-    if (s->batch) dpd_batch_destroy(s->batch);
+    for (dpd_batch b : s->batch)
+        if (b) dpd_batch_destroy(b);
     for (Req* r : s->active)
         if (r->box) dpd::box_release(r->box);
     for (Retiring& g : s->retiring) {

@@ -18,7 +18,8 @@ def _run(cells, pos, vel, params, seed, steps, tile=None, reference=False, threa
     if tile is not None:
         b.set_tile(tile)
     b.set_force_threads(threads)
-    assert b.get_force_threads() == (threads or 512)
+    if threads or tile is not None:
+        assert b.get_force_threads() == (threads or 512)
     b.set_state(pos, vel)
     b.step(steps)
     out = (b.read(dpd.FORCE), b.read(dpd.POS), b.read(dpd.VEL))
@@ -108,6 +109,18 @@ def test_large_box_tiled_equals_reference():
     til = _run(cells, pos, vel, P3, 25, 3)
     for a, b in zip(til, ref):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("cells,n,tile,threads", [
+    ((48, 48, 48), 3 * 48 ** 3, (6, 6, 4), 1024),     # large dilute box: the large shape
+    ((16, 16, 16), 3 * 16 ** 3, (4, 4, 4), 512),      # small: more, smaller tiles
+    ((64, 64, 64), 8 * 64 ** 3, (8, 4, 4), 1024),     # large dense box
+    ((12, 10, 9), 8 * 1080, (4, 2, 2), 512),          # small dense box
+])
+def test_default_tile_follows_density_and_size(cells, n, tile, threads):
+    b = dpd.Box(cells, n, params=dpd.make_params(), seed=1)
+    assert b.get_tile() == tile and b.get_force_threads() == threads
+    b.close()
 
 
 def test_bad_tile_rejected():
