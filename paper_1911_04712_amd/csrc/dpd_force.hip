@@ -27,6 +27,7 @@
 // Bitwise agreement of the two kernels follows from the rules in
 // dpd_device.hpp: exact displacements, exactly antisymmetric pair forces and
 // order-independent fixed-point sums.
+#include <climits>
 #include <cmath>
 
 #include "dpd_internal.hpp"
@@ -188,12 +189,57 @@ __device__ __forceinline__ int small_div(int x, float inv)
     return (int)(((float)x + 0.5f) * inv);
 }
 
+// 64-bit value moved by a DPP row operation (both halves with the same
+// control); lanes whose source lies outside their row of 16 get 0.
+template <int kCtrl>
+__device__ __forceinline__ long long dpp_i64(long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), kCtrl, 0xf, 0xf, true);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Levels of the home-side pre-combine in a flush (0: every lane adds its own
+// pair force to its home particle).  The hits of one home particle sit
+// together in the queue, so a flush's lanes target a few home accumulators
+// many times over, and LDS atomics to one address serialise.  Level k adds,
+// inside aligned groups of 2^levels lanes, the partial sum of the lanes
+// 2^(k-1) below when no run of another home starts in between (a segmented
+// scan by DPP row shifts); then only the last lane of each run of one home
+// inside a group adds the run's sum.  Integer sums: the bits do not change.
+#ifndef DPD_HOME_COMBINE
+#define DPD_HOME_COMBINE 2
+#endif
+constexpr int kHomeCombine = DPD_HOME_COMBINE;
+static_assert(kHomeCombine >= 0 && kHomeCombine <= 4, "groups of at most one DPP row (16 lanes)");
+
+// One level of the segmented scan at distance kDist (DPP row_shr:kDist):
+// a lane whose run started more than kDist lanes back adds the partial sums
+// kDist lanes below; `head` becomes "a run starts within the last 2 kDist
+// lanes".
+template <int kDist>
+__device__ __forceinline__ void combine_level(long long& hx, long long& hy, long long& hz, int& head)
+{
+    constexpr int ctrl = 0x110 + kDist;                      // row_shr:kDist
+    const int hb = __builtin_amdgcn_update_dpp(1, head, ctrl, 0xf, 0xf, false);
+    const long long tx = dpp_i64<ctrl>(hx), ty = dpp_i64<ctrl>(hy), tz = dpp_i64<ctrl>(hz);
+    const bool add = head == 0;
+    hx += add ? tx : 0ll;
+    hy += add ? ty : 0ll;
+    hz += add ? tz : 0ll;
+    head |= hb;
+}
+
 // Staged velocity .w: the tile index (-1 outside the tile); with species
 // (kSp) its low 24 bits hold the tile index and the top 8 bits the species.
+// Every lane of the wave calls it; `live` marks the lanes that hold a queue
+// entry (the others take entry 0, a coincident pair that adds nothing, and
+// skip the atomics).
 template <bool kSp>
-__device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const float4* sv, long long* acc,
+__device__ __forceinline__ void flush_hit(unsigned e, bool live, const float4* sp, const float4* sv, long long* acc,
                                           uint32_t step, const PairConst& pc, const float4* tab, bool& bad)
 {
+    if (!live) e = 0u;
     const int a = (int)(e >> 16), b = (int)(e & 0xffffu);
     const float4 va = sv[a], vb = sv[b];
     long long fx, fy, fz;
@@ -213,12 +259,29 @@ __device__ __forceinline__ void flush_hit(unsigned e, const float4* sp, const fl
         ia = wa;
         ib = wb;
     }
-    // tile indices are below 2^24: 24-bit multiplies for the LDS offsets
-    unsigned long long* pa = (unsigned long long*)((char*)acc + __umul24((unsigned)ia, 24u));
-    atomicAdd(pa, (unsigned long long)fx);
-    atomicAdd(pa + 1, (unsigned long long)fy);
-    atomicAdd(pa + 2, (unsigned long long)fz);
-    if (ib >= 0) {                       // both ends in the tile: apply the reaction too
+    long long hx = fx, hy = fy, hz = fz;
+    bool home_add = live;
+    if constexpr (kHomeCombine > 0) {
+        constexpr int last = (1 << kHomeCombine) - 1;        // lanes per group - 1
+        const int g = (int)(threadIdx.x & 63) & last;
+        const int key = live ? ia : -1 - (int)(threadIdx.x & 63);   // dead lanes never match
+        const int kp1 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x111, 0xf, 0xf, false);   // row_shr:1
+        const int kn1 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x101, 0xf, 0xf, false);   // row_shl:1
+        int head = (g == 0 || kp1 != key) ? 1 : 0;           // a run of one home starts here
+        combine_level<1>(hx, hy, hz, head);
+        if constexpr (kHomeCombine > 1) combine_level<2>(hx, hy, hz, head);
+        if constexpr (kHomeCombine > 2) combine_level<4>(hx, hy, hz, head);
+        if constexpr (kHomeCombine > 3) combine_level<8>(hx, hy, hz, head);
+        home_add = live && (g == last || kn1 != key);
+    }
+    if (home_add) {
+        // tile indices are below 2^24: 24-bit multiplies for the LDS offsets
+        unsigned long long* pa = (unsigned long long*)((char*)acc + __umul24((unsigned)ia, 24u));
+        atomicAdd(pa, (unsigned long long)hx);
+        atomicAdd(pa + 1, (unsigned long long)hy);
+        atomicAdd(pa + 2, (unsigned long long)hz);
+    }
+    if (live && ib >= 0) {               // both ends in the tile: apply the reaction too
         unsigned long long* pb = (unsigned long long*)((char*)acc + __umul24((unsigned)ib, 24u));
         atomicAdd(pb, (unsigned long long)(-fx));
         atomicAdd(pb + 1, (unsigned long long)(-fy));
@@ -607,7 +670,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
                     __builtin_amdgcn_wave_barrier();
                     int fh = 0;
                     do {
-                        flush_hit<kSp>(q[fh + lane], sp, sv, acc, step, pc, tab, bad);
+                        flush_hit<kSp>(q[fh + lane], true, sp, sv, acc, step, pc, tab, bad);
                         fh += 64;
                     } while (qt - fh >= 64);
                     const unsigned rest = q[fh + lane];          // move what is left (< 64) to the front
@@ -674,7 +737,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < qt) flush_hit<kSp>(q[lane], sp, sv, acc, step, pc, tab, bad);
+    if (qt > 0) flush_hit<kSp>(q[lane], lane < qt, sp, sv, acc, step, pc, tab, bad);
     if (bad) atomicOr(nonfinite, 1);
     __syncthreads();
 

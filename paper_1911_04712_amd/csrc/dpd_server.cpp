@@ -254,12 +254,12 @@ int materialise(dpd_server_s* s, Req* r)
     if (rc) return pass(rc, "dpd_server: create");
     r->box = b;
     if ((rc = dpd_set_params(b, &r->params)) || (rc = dpd_set_seed(b, r->seed))) return pass(rc, "dpd_server: setup");
-    // every box of a class batch at one launch shape: the small-box default
-    // of its density class (a large box alone would take a larger tile, whose
-    // LDS reservation the whole batch would then carry)
-    // (a fluid too dense for that shape's LDS keeps the box's own default)
-    static const int32_t kTile[dpd_server_s::kClasses][3] = {{4, 4, 4}, {4, 2, 2}};
-    if (dpd_set_force_threads(b, 512) != DPD_OK || dpd_set_tile(b, kTile[density_class(r)]) != DPD_OK) {
+    // every box of a class batch at one launch shape, the fastest of a sweep
+    // over batches of the served mix's boxes (MI355X): 6x6x4 cells for the
+    // dilute class, 4x4x2 for the dense one, 1024 threads each (a fluid too
+    // dense for that shape's LDS keeps the box's own default)
+    static const int32_t kTile[dpd_server_s::kClasses][3] = {{6, 6, 4}, {4, 4, 2}};
+    if (dpd_set_force_threads(b, 1024) != DPD_OK || dpd_set_tile(b, kTile[density_class(r)]) != DPD_OK) {
         static const int32_t kDefault[3] = {0, 0, 0};
         if ((rc = dpd_set_force_threads(b, 0)) || (rc = dpd_set_tile(b, kDefault))) return pass(rc, "dpd_server: tile");
     }

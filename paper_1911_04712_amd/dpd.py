@@ -366,8 +366,9 @@ class Box:
         return ms.value
 
     def profile_steps(self, nsteps):
-        """Mean device ms per step of each stage (bin, force, virial, integrate),
-        timed with HIP events around eager launches."""
+        """Mean device ms per step of each stage (bin, force, virial, integrate)
+        of eager steps, timed by events that each stage's first kernel records
+        as it starts and its last as it ends."""
         ms = np.zeros(4)
         _check(lib().dpd_profile_steps(self._h, int(nsteps), ms.ctypes.data_as(ctypes.c_void_p)))
         return dict(zip(("bin", "force", "virial", "integrate"), ms.tolist()))
