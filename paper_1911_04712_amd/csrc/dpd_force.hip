@@ -208,7 +208,7 @@ __device__ __forceinline__ long long dpp_i64(long long v)
 // scan by DPP row shifts); then only the last lane of each run of one home
 // inside a group adds the run's sum.  Integer sums: the bits do not change.
 #ifndef DPD_HOME_COMBINE
-#define DPD_HOME_COMBINE 2
+#define DPD_HOME_COMBINE 3
 #endif
 constexpr int kHomeCombine = DPD_HOME_COMBINE;
 static_assert(kHomeCombine >= 0 && kHomeCombine <= 4, "groups of at most one DPP row (16 lanes)");
