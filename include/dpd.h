@@ -359,7 +359,7 @@ int dpd_destroy(dpd_box box);
  * fused).  Each stage is timed by events that its first kernel records as it
  * starts and its last as it ends (hipExtLaunchKernel), so the times are the
  * kernels' own, from the first one's start to the last one's end.  The fold
- * of the reductions, which a graph runs inside the next step's scan, runs
+ * of the reductions, which a graph runs inside the next step's gather, runs
  * after the timed stages.  The steps advance the box like dpd_step.
  * Synchronises. */
 int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);

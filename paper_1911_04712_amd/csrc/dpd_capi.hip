@@ -1094,7 +1094,7 @@ int dpd_profile_steps(dpd_box b, int64_t nsteps, double* ms_out)
         const bool vir = b->lp.any_virial && b->lp.total[dpd::kWPart] > 0, integ = !b->lp.fuse;
         if (e == hipSuccess && vir) e = dpd::launch_virial(b->lp, b->stream, ev[4], ev[5]);
         if (e == hipSuccess && integ) e = dpd::launch_integrate(b->lp, b->stream, ev[6], ev[7]);
-        // the reductions' fold normally rides in the next step's scan: here
+        // the reductions' fold normally rides in the next step's gather: here
         // it runs after the timed stages
         if (e == hipSuccess) e = dpd::launch_fold(b->lp, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

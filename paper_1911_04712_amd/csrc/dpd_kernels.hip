@@ -314,14 +314,21 @@ int integrate_blocks(int n)
     return b > kIntegrateMaxBlocks ? kIntegrateMaxBlocks : b;
 }
 
+// Blocks of the per-particle kernels: every particle, and every chunk sum
+// that k_scatter zeroes.  The gather launch has one block more, which folds
+// the previous step's reductions (hidden behind the gather's own work).
+__host__ __device__ inline int part_blocks(const BoxDesc& d)
+{
+    const int np = (d.n + kBlock - 1) / kBlock, nk = (d.nsub + kBlock - 1) / kBlock;
+    return np > nk ? np : nk;
+}
+
 int box_work(const BoxDesc& d, int kind)
 {
     switch (kind) {
-    case kWChunk: return d.nchunks + 1;                      // + one block that folds the reductions
-    case kWPart: {                                           // also covers the chunk sums k_scatter zeroes
-        const int np = (d.n + kBlock - 1) / kBlock, nk = (d.nsub + kBlock - 1) / kBlock;
-        return np > nk ? np : nk;
-    }
+    case kWChunk: return d.nchunks;
+    case kWPart: return part_blocks(d) + 1;                   // + one block that folds the reductions
+
     case kWTile: return ((d.tc.ntiles + 7) / 8) * 8;       // padded for the XCD swizzle
     default: return d.nblk_int;
     }
@@ -335,10 +342,6 @@ __global__ __launch_bounds__(kBlock) void k_scan(const BoxDesc* __restrict__ des
     constexpr int per = kScanChunk / kBlock;   // consecutive cells per thread
     __shared__ int scratch[kBlock / 64];
     __shared__ int wtot[kBlock / 64];
-    if (lb == d.nchunks) {                      // the extra block: the previous step's reductions
-        fold_stats(d);
-        return;
-    }
     const int nc = d.nc;
     int* __restrict__ count = d.count;
     // this chunk's counts first: their loads overlap the prefix below
@@ -402,6 +405,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
                                                    int nbox)
 {
     DPD_BOX_OF(kWPart)
+    if (lb == part_blocks(d)) {                 // the extra block: the previous step's reductions
+        fold_stats(d);
+        return;
+    }
     const int p = lb * kBlock + threadIdx.x;
     if (p >= d.n) return;
     const int* __restrict__ perm = d.perm;
