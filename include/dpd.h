@@ -61,7 +61,8 @@ enum {
     DPD_ENOMEM = -2,     /* workspace or pool too small; host allocation failed */
     DPD_EDEVICE = -3,    /* a HIP call failed; message in dpd_last_error()     */
     DPD_ESTATE = -4,     /* call out of order (e.g. step before set_state)     */
-    DPD_ENONFINITE = -5, /* a non-finite force, velocity or position was seen  */
+    DPD_ENONFINITE = -5, /* a non-finite force, velocity or position, or a    */
+                         /* pair force of magnitude >= 2^19, was seen          */
     DPD_EAGAIN = -6,     /* result not ready yet                                */
     DPD_EBUSY = -7,      /* no free slot or memory right now                    */
     DPD_ENOTFOUND = -8   /* unknown ticket                                      */

@@ -11,7 +11,7 @@
 //  * the pair force is an odd function of (r_ij, v_ij) in FP32: negating both
 //    negates every product feeding e_ij . v_ij exactly, so F_ji == -F_ij;
 //  * forces are accumulated in 64-bit fixed point (2^31 units per force
-//    unit) with a truncating, odd-symmetric conversion, so sums are exact
+//    unit) with a round-to-nearest-even, odd-symmetric conversion, so sums are exact
 //    integers whose value does not depend on summation order.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -64,14 +64,20 @@ __device__ __forceinline__ float pair_xi(uint32_t id_i, uint32_t id_j, uint32_t 
 // ---- fixed point ---------------------------------------------------------
 constexpr float kFxScale = 0x1p31f;        // units per force unit
 constexpr double kFxInv = 0x1p-31;
-constexpr float kFxLimit = 0x1p30f;        // |F| beyond this is reported as non-finite
+constexpr float kFxLimit = 0x1p19f;        // a pair force of |F| >= 2^19 is reported as non-finite
+constexpr double kFxMagic = 0x1.8p52;      // 1.5 * 2^52
+constexpr int kFxMagicHi = 0x43380000;     // its high word (the low word is 0)
 
-// Truncating conversion: fx(-f) == -fx(f).  Requires |f| < 2^30.
-__device__ __forceinline__ long long fx_of(float f)
+// Fixed-point value of a force already scaled to units, g = F * 2^31 with
+// |g| < 2^51: the nearest integer, ties to even, so fx(-g) == -fx(g).  In
+// [2^52, 2^53) doubles are spaced by 1, so g + 1.5 * 2^52 rounds g to an
+// integer held in the low mantissa bits; taking off the magic number's bits
+// leaves that integer (two's complement, since |g| < 2^51).
+__device__ __forceinline__ long long fx_of_units(float g)
 {
-    const float hi = truncf(f);
-    const float lo = (f - hi) * kFxScale;          // exact, |lo| < 2^31
-    return ((long long)(int)hi << 31) + (long long)(int)lo;
+    const long long b = __double_as_longlong((double)g + kFxMagic);
+    const int hi = (int)(b >> 32) - kFxMagicHi;
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)b);
 }
 
 struct PairConst {

@@ -84,13 +84,18 @@ __device__ __forceinline__ bool pair_fx(float4 pi, float4 vi, float4 pj, float4 
     // coincident particles exert no force on each other; with a pair cutoff
     // the candidate test (r < 1) lets through pairs beyond it
     const bool live = r2 > 0.0f && (!kCut || r2 < 1.0f);
-    const float Fx = live ? fs * (dx * rinv) : 0.0f, Fy = live ? fs * (dy * rinv) : 0.0f,
-                Fz = live ? fs * (dz * rinv) : 0.0f;
-    // out of the fixed-point range (or NaN): adds nothing, reported (selects, not a branch)
-    const bool ok = fabsf(Fx) < kFxLimit && fabsf(Fy) < kFxLimit && fabsf(Fz) < kFxLimit;
-    fx = fx_of(ok ? Fx : 0.0f);
-    fy = fx_of(ok ? Fy : 0.0f);
-    fz = fx_of(ok ? Fz : 0.0f);
+    // the scalar force in fixed-point units (a power-of-two scale: each
+    // component below is 2^31 times its FP32 value F = fs (d / r), bit for
+    // bit).  |e| <= 1 up to an ulp, so |fs| < 2^19 keeps every component
+    // inside the conversion's range; beyond it (or NaN) the pair adds
+    // nothing and is reported (selects, not a branch)
+    const float g = fs * kFxScale;
+    const bool ok = !live || fabsf(g) < kFxLimit * kFxScale;
+    const float gs = (live && ok) ? g : 0.0f;
+    const float ri = live ? rinv : 0.0f;
+    fx = fx_of_units(gs * (dx * ri));
+    fy = fx_of_units(gs * (dy * ri));
+    fz = fx_of_units(gs * (dz * ri));
     return ok;
 }
 
