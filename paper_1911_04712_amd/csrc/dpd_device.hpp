@@ -40,6 +40,33 @@ __host__ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_
     return c;
 }
 
+// a ^ b ^ k in one instruction: gfx950's three-input bitwise operation with
+// the truth table of a three-way xor (0x96, symmetric in its inputs).  k must
+// be the same on every lane of the wave (it is passed in a scalar register).
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// philox10 for a key that is the same on every lane of the wave (the pair
+// term's seed): the same words, with each round's two xors into the key
+// fused into one instruction per word.
+__device__ __forceinline__ uint4 philox10_uniform_key(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhM0 * c.x;
+        const uint64_t p1 = (uint64_t)kPhM1 * c.z;
+        c = make_uint4(xor3_uniform((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       xor3_uniform((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+        k0 += kPhW0;
+        k1 += kPhW1;
+    }
+    return c;
+}
+
 // Gaussian xi from the first two Philox words (Box-Muller on 24-bit
 // uniforms u1 in (0, 1], u2 in [0, 1)).  v_log_f32 returns log2 and
 // v_cos_f32 takes its argument in revolutions, so cos(2 pi u2) needs no
@@ -53,11 +80,12 @@ __device__ __forceinline__ float box_muller(uint32_t w0, uint32_t w1)
     return rad * __builtin_amdgcn_cosf(u2);
 }
 
+// k0, k1 (the seed) are the same on every lane of the wave.
 __device__ __forceinline__ float pair_xi(uint32_t id_i, uint32_t id_j, uint32_t step, uint32_t k0,
                                          uint32_t k1)
 {
     const uint32_t lo = min(id_i, id_j), hi = max(id_i, id_j);
-    const uint4 w = philox10(make_uint4(lo, hi, step, 0u), k0, k1);
+    const uint4 w = philox10_uniform_key(make_uint4(lo, hi, step, 0u), k0, k1);
     return box_muller(w.x, w.y);
 }
 

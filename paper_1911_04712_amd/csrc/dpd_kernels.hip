@@ -817,7 +817,11 @@ __global__ void k_philox(const uint32_t* __restrict__ ctr4, const uint32_t* __re
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint4 c = make_uint4(ctr4[4 * i], ctr4[4 * i + 1], ctr4[4 * i + 2], ctr4[4 * i + 3]);
-    const uint4 w = philox10(c, key2[2 * i], key2[2 * i + 1]);
+    const uint32_t k0 = key2[2 * i], k1 = key2[2 * i + 1];
+    // a wave whose lanes share one key takes the force kernels' variant
+    const uint32_t u0 = __builtin_amdgcn_readfirstlane(k0), u1 = __builtin_amdgcn_readfirstlane(k1);
+    const bool same = __builtin_amdgcn_ballot_w64(k0 != u0 || k1 != u1) == 0;
+    const uint4 w = same ? philox10_uniform_key(c, u0, u1) : philox10(c, k0, k1);
     out4[4 * i] = w.x;
     out4[4 * i + 1] = w.y;
     out4[4 * i + 2] = w.z;
