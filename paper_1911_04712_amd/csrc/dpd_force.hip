@@ -171,8 +171,10 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restri
 // ---------------------------------------------------------------------------
 // tiled kernel
 // ---------------------------------------------------------------------------
-constexpr int kQueueLive = 192; // per-wave hit queue: < 64 pending + up to 2 x 64 new ...
-constexpr int kQueue = 256;     // ... then 64 slots that lanes without a hit write to
+constexpr int kQueueLive = 192; // per-wave hit queue: < 64 pending + up to 2 x 64 new; after the
+                                // waves' queues, 64 slots that lanes without a hit write to (shared
+                                // by all waves: nothing reads them)
+constexpr int kUnitSlots = 16;  // run-table entries per home unit (14 runs, own_e, the list length)
 
 // Inclusive prefix sum inside each row of 16 lanes (DPP row shifts).
 __device__ __forceinline__ int row16_incl_scan(int v)
@@ -434,6 +436,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
     int* cg = (int*)(lds + tc.off_cg);                          // staged cell start in HBM (cell order)
     int4* rows = (int4*)(lds + tc.off_rows);                    // tile rows: (lds start, len, HBM start, tile start)
     unsigned* qall = (unsigned*)(lds + tc.off_q);               // per-wave hit queues
+    unsigned* utab = (unsigned*)(lds + tc.off_ut);              // run table of every home unit
     __shared__ int s_scr[kThreads / 64];
     __shared__ int s_unit;                                      // next home unit to hand out
     const float4* tab = nullptr;                                // species pair table (kSp)
@@ -573,84 +576,96 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
             }
         }
     }
+    // 4a. the candidate list of every home unit (ux consecutive cells x ..
+    //     x+w-1 of a tile row, w = ux or fewer at the row's end), sixteen
+    //     lanes per unit with every lane busy: up to 14 runs of consecutive
+    //     staged particles, one per slot,
+    //       slot 0      the unit and cell x+w (so the unit comes first)
+    //       slots 1-4   forward rows, cells x-1 .. x+w
+    //       slots 5-8   backward rows (y-1, z), (y+1, z-1), (y, z-1),
+    //                   (y-1, z-1): cells x-1 .. x+w when the row lies in the
+    //                   halo, else cell x-1 when it is a halo cell
+    //       slots 9-12  the same backward rows: cell x+w when it is a halo cell
+    //       slot 13     cell x-1 of the own row when it is a halo cell
+    //     Each entry holds the run's staged start (high 16 bits) and its
+    //     position in the list (low 16 bits, an exclusive scan over the
+    //     unit's sixteen lanes, which are one DPP row); slot 14 holds the
+    //     end of the unit's own particles in place of a run start, and the
+    //     position of slots 14 and 15 is the list length.  Staged indices
+    //     are below smax <= 65535, so both halves fit.
+    const int upr = (P0 + ux - 1) / ux;                 // units per tile row
+    const int nunits = upr * nrows;
+    {
+        const int sl = lane & (kUnitSlots - 1);
+        const int rj = (sl - 1) & 3;                    // stencil row of slots 1..12
+        const int fdy = (rj == 0 || rj == 3) ? 1 : (rj == 1 ? -1 : 0), fdz = rj == 0 ? 0 : 1;
+        const int rsgn = (sl == 0 || sl >= 13) ? 0 : (sl < 5 ? 1 : -1);
+        const int roff = rsgn * S0 * (fdy + S1 * fdz);  // staged-cell offset of the slot's row
+        const float inv_upr = 1.0f / (float)upr;
+        // whole units per pass (kThreads is a multiple of 16): the scan's
+        // row of sixteen lanes is all active or all idle
+        for (int e = tid; e < kUnitSlots * nunits; e += kThreads) {
+            const int un = e / kUnitSlots;
+            const int row = small_div(un, inv_upr);     // row (y, z) of the unit, y fastest
+            const int rz = small_div(row, inv_p1), ry = row - rz * P1;
+            const int lx = 1 + (un - row * upr) * ux, ly = ry + 1, lz = rz + 1;
+            const int w = min(ux, P0 + 1 - lx);         // cells in this unit
+            const int cown = lx + S0 * (ly + S1 * lz);
+            // which backward rows (slots 5-8, and 9-12) leave the tile
+            const bool yl = ly == 1, yh = ly == P1, zl = lz == 1;
+            const unsigned outB = ((unsigned)yl << 5) | ((unsigned)(yh || zl) << 6) | ((unsigned)zl << 7) |
+                                  ((unsigned)(yl || zl) << 8);
+            const bool xl = lx == 1, xh = lx + w - 1 == P0;
+            const unsigned mLeft = xl ? ((0x1E0u & ~outB) | (1u << 13)) : 0u;
+            const unsigned mRight = xh ? (0x1E00u & ~(outB << 4)) : 0u;
+            const unsigned mOn = 0x1Fu | outB | mLeft | mRight;
+            const bool left = (mLeft >> sl) & 1u, right = (mRight >> sl) & 1u, on = (mOn >> sl) & 1u;
+            // run of this slot: cells x0..x1 relative to the unit's first cell
+            const int x0 = right ? w : (sl == 0 ? 0 : -1);
+            const int x1 = left ? -1 : w;
+            const int rbase = cown + roff;
+            const int rs = cst[rbase + x0];
+            const int rl = on ? cst[rbase + x1 + 1] - rs : 0;
+            const int rpre = row16_incl_scan(rl) - rl;
+            const int start = sl == 14 ? cst[cown + w] : rs;
+            utab[e] = ((unsigned)start << 16) | (unsigned)rpre;
+        }
+    }
     for (int k = tid; k < 3 * nt; k += kThreads) acc[k] = 0;
     if (tid == 0) s_unit = nw;                          // units 0 .. nw-1 start the waves
     __syncthreads();
 
-    // 4. candidates, one home unit per wave at a time: ux consecutive cells
-    //    x .. x+w-1 of a tile row (w = ux, or fewer at the row's end).  All
-    //    particles of a unit share one candidate list: the unit itself and
-    //    its half stencil (cell x+w, rows (y+1, z) and (y-1..y+1, z+1) over
-    //    x-1 .. x+w), plus the backward cells that lie in the halo (pairs
-    //    that cross the tile boundary are evaluated from both tiles, each
-    //    updating only its own particle).  The list is up to 14 runs of
-    //    consecutive staged particles, one per lane of the run table:
-    //      slot 0      the unit and cell x+w (so the unit comes first)
-    //      slots 1-4   forward rows, cells x-1 .. x+w
-    //      slots 5-8   backward rows (y-1, z), (y+1, z-1), (y, z-1),
-    //                  (y-1, z-1): cells x-1 .. x+w when the row lies in the
-    //                  halo, else cell x-1 when it is a halo cell
-    //      slots 9-12  the same backward rows: cell x+w when it is a halo cell
-    //      slot 13     cell x-1 of the own row when it is a halo cell
-    //    Entries out of reach of a given particle fail the distance test.
+    // 4b. candidates, one home unit per wave at a time.  All particles of a
+    //    unit share one candidate list: the unit itself and its half stencil
+    //    (cell x+w, rows (y+1, z) and (y-1..y+1, z+1) over x-1 .. x+w), plus
+    //    the backward cells that lie in the halo (pairs that cross the tile
+    //    boundary are evaluated from both tiles, each updating only its own
+    //    particle), as laid out in the run table above.  Entries out of
+    //    reach of a given particle fail the distance test.
     //    List entries are spread over the lanes, each home particle is tested
     //    against all of them, and hits with r < r_c are compacted into a
     //    per-wave queue (ballot + popcount) and evaluated 64 at a time with
     //    every lane busy.  A pair inside the tile adds F_ij to i and -F_ij to
     //    j.  Pairs inside the unit are taken once (b after a): the unit heads
     //    the list in cell order, so that is list position > index of a.
-    unsigned* q = qall + wave * kQueue;                 // queue, entries [0, qt); lanes without a hit
-    int qt = 0;                                         // write to q[kQueueLive + lane]; qt is wave-uniform
+    unsigned* q = qall + wave * kQueueLive;             // queue, entries [0, qt); qt is wave-uniform
+    int qt = 0;
     bool bad = false;
-    const int rj = (lane - 1) & 3;                      // stencil row of slots 1..12
-    const int fdy = (rj == 0 || rj == 3) ? 1 : (rj == 1 ? -1 : 0), fdz = rj == 0 ? 0 : 1;
-    const int rsgn = (lane == 0 || lane >= 13) ? 0 : (lane < 5 ? 1 : -1);
-    const int roff = rsgn * S0 * (fdy + S1 * fdz);      // staged-cell offset of the slot's row
-    int rs_ = 0, rl_ = 0;
-    // home units (ux consecutive cells of a tile row) go to the waves in turn
-    const int upr = (P0 + ux - 1) / ux;                 // units per tile row
-    const int nunits = upr * nrows;
     // each wave takes the next unit when it is done with one (face rows
     // cost about twice an interior row, so a fixed deal of units to waves
     // leaves waves idle while the slowest finishes)
-    const float inv_upr = 1.0f / (float)upr;
     auto next_unit = [&]() {
         int v = 0;
         if (lane == 0) v = atomicAdd(&s_unit, 1);
         return __builtin_amdgcn_readfirstlane(v);
     };
     for (int un = wave; un < nunits; un = next_unit()) {
-        const int row = small_div(un, inv_upr);         // row (y, z) of the unit, y fastest
-        const int rz = small_div(row, inv_p1), ry = row - rz * P1;
-        const int lx = 1 + (un - row * upr) * ux, ly = ry + 1, lz = rz + 1;
-        const int w = min(ux, P0 + 1 - lx);             // cells in this unit
-        const int cown = lx + S0 * (ly + S1 * lz);
-        const int own_s = __builtin_amdgcn_readfirstlane(cst[cown]);
-        const int own_e = __builtin_amdgcn_readfirstlane(cst[cown + w]);
+        const unsigned ent = utab[un * kUnitSlots + (lane & (kUnitSlots - 1))];
+        const int rs = (int)(ent >> 16), rpre = (int)(ent & 0xffffu);
+        const int own_s = __builtin_amdgcn_readlane(rs, 0);
+        const int own_e = __builtin_amdgcn_readlane(rs, 14);
         if (own_s == own_e) continue;
-        {
-            // which backward rows (slots 5-8, and 9-12) leave the tile
-            const bool yl = ly == 1, yh = ly == P1, zl = lz == 1;
-            const unsigned long long outB = ((unsigned long long)yl << 5) | ((unsigned long long)(yh || zl) << 6) |
-                                            ((unsigned long long)zl << 7) | ((unsigned long long)(yl || zl) << 8);
-            const bool xl = lx == 1, xh = lx + w - 1 == P0;
-            const unsigned long long mLeft = xl ? ((0x1E0ull & ~outB) | (1ull << 13)) : 0ull;
-            const unsigned long long mRight = xh ? (0x1E00ull & ~(outB << 4)) : 0ull;
-            const unsigned long long mOn = 0x1Full | outB | mLeft | mRight;
-            const bool left = __builtin_amdgcn_inverse_ballot_w64(mLeft);
-            const bool right = __builtin_amdgcn_inverse_ballot_w64(mRight);
-            const bool on = __builtin_amdgcn_inverse_ballot_w64(mOn);
-            // run of this slot: cells x0..x1 relative to the unit's first cell
-            const int x0 = right ? w : (lane == 0 ? 0 : -1);
-            const int x1 = left ? -1 : w;
-            const int rbase = cown + roff;
-            rs_ = cst[rbase + x0];
-            rl_ = on ? cst[rbase + x1 + 1] - rs_ : 0;
-        }
-        const int rs = rs_, rl = rl_;
-        const int rincl = row16_incl_scan(rl);
-        const int rpre = rincl - rl;
-        const int M = __builtin_amdgcn_readlane(rincl, 15);
+        const int M = __builtin_amdgcn_readlane(rpre, 15);
         const int delta = rs - rpre;                // staged index = list position + delta
         for (int u0 = 0; u0 < M; u0 += 64) {
             // a last stretch of at most 32 entries is tested by lane groups
@@ -668,7 +683,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
             const float4 xb = sp[b];
             const float bx = valid ? xb.x : 1e30f;
             const unsigned ub = (unsigned)u;
-            const unsigned qdummy = (unsigned)(kQueueLive + lane);
+            const unsigned qdummy = (unsigned)((nw - wave) * kQueueLive + lane);   // the shared slots
             // flush whole waves of hits once 64 or more are queued
             auto drain = [&]() {
                 if (qt >= 64) {
@@ -793,8 +808,10 @@ TileConst make_tile_const(const int* cells, double rho, const int* tile, int thr
     off += ((size_t)ncs_max * 4 + 15) & ~(size_t)15;
     tc.off_rows = (int)off;
     off += (size_t)tc.T[1] * tc.T[2] * 16;
+    tc.off_ut = (int)off;
+    off += (size_t)((tc.T[0] + tc.ux - 1) / tc.ux) * tc.T[1] * tc.T[2] * kUnitSlots * 4;
     tc.off_q = (int)off;
-    off += (size_t)(threads / 64) * kQueue * 4;
+    off += ((size_t)(threads / 64) * kQueueLive + 64) * 4;
     tc.lds_bytes = (int)off;
     return tc;
 }

@@ -141,7 +141,7 @@ struct TileConst {
     int smax;          // staged particles (tile + halo) that fit the LDS buffers
     int pmax;          // tile particles that fit the accumulators
     int lds_bytes;
-    int off_sv, off_acc, off_cst, off_cg, off_rows, off_q;
+    int off_sv, off_acc, off_cst, off_cg, off_rows, off_ut, off_q;
     int threads;       // workgroup size the queue region is laid out for (a kForceBlocks entry)
 };
 
