@@ -220,21 +220,32 @@ __device__ __forceinline__ long long dpp_i64(long long v)
 constexpr int kHomeCombine = DPD_HOME_COMBINE;
 static_assert(kHomeCombine >= 0 && kHomeCombine <= 4, "groups of at most one DPP row (16 lanes)");
 
+// Lanes that open a group of 2^levels lanes, as a wave mask.
+constexpr unsigned long long group_first_lanes(int levels)
+{
+    unsigned long long m = 0;
+    for (int l = 0; l < 64; l += 1 << levels) m |= 1ull << l;
+    return m;
+}
+
 // One level of the segmented scan at distance kDist (DPP row_shr:kDist):
 // a lane whose run started more than kDist lanes back adds the partial sums
-// kDist lanes below; `head` becomes "a run starts within the last 2 kDist
-// lanes".
+// kDist lanes below.  The run heads are a wave mask (bit l for lane l); after
+// the level a lane's bit says "a run starts within the last 2 kDist lanes",
+// which is its bit or the bit kDist lanes below (a lane whose source lies in
+// the row of 16 below counts as a head: rows are never crossed).  The mask
+// arithmetic runs on the scalar unit.
 template <int kDist>
-__device__ __forceinline__ void combine_level(long long& hx, long long& hy, long long& hz, int& head)
+__device__ __forceinline__ void combine_level(long long& hx, long long& hy, long long& hz, unsigned long long& heads)
 {
     constexpr int ctrl = 0x110 + kDist;                      // row_shr:kDist
-    const int hb = __builtin_amdgcn_update_dpp(1, head, ctrl, 0xf, 0xf, false);
+    constexpr unsigned long long kRowLow = ((1ull << kDist) - 1ull) * 0x0001000100010001ull;   // l % 16 < kDist
     const long long tx = dpp_i64<ctrl>(hx), ty = dpp_i64<ctrl>(hy), tz = dpp_i64<ctrl>(hz);
-    const bool add = head == 0;
+    const bool add = !__builtin_amdgcn_inverse_ballot_w64(heads);
     hx += add ? tx : 0ll;
     hy += add ? ty : 0ll;
     hz += add ? tz : 0ll;
-    head |= hb;
+    heads |= ((heads << kDist) & ~kRowLow) | kRowLow;
 }
 
 // Staged velocity .w: the tile index (-1 outside the tile); with species
@@ -274,11 +285,12 @@ __device__ __forceinline__ void flush_hit(unsigned e, bool live, const float4* s
         const int key = live ? ia : -1 - (int)(threadIdx.x & 63);   // dead lanes never match
         const int kp1 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x111, 0xf, 0xf, false);   // row_shr:1
         const int kn1 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x101, 0xf, 0xf, false);   // row_shl:1
-        int head = (g == 0 || kp1 != key) ? 1 : 0;           // a run of one home starts here
-        combine_level<1>(hx, hy, hz, head);
-        if constexpr (kHomeCombine > 1) combine_level<2>(hx, hy, hz, head);
-        if constexpr (kHomeCombine > 2) combine_level<4>(hx, hy, hz, head);
-        if constexpr (kHomeCombine > 3) combine_level<8>(hx, hy, hz, head);
+        // a run of one home starts here: a group's first lane, or a new key
+        unsigned long long heads = __builtin_amdgcn_ballot_w64(kp1 != key) | group_first_lanes(kHomeCombine);
+        combine_level<1>(hx, hy, hz, heads);
+        if constexpr (kHomeCombine > 1) combine_level<2>(hx, hy, hz, heads);
+        if constexpr (kHomeCombine > 2) combine_level<4>(hx, hy, hz, heads);
+        if constexpr (kHomeCombine > 3) combine_level<8>(hx, hy, hz, heads);
         home_add = live && (g == last || kn1 != key);
     }
     if (home_add) {
@@ -288,11 +300,11 @@ __device__ __forceinline__ void flush_hit(unsigned e, bool live, const float4* s
         atomicAdd(pa + 1, (unsigned long long)hy);
         atomicAdd(pa + 2, (unsigned long long)hz);
     }
-    if (live && ib >= 0) {               // both ends in the tile: apply the reaction too
+    if (live && ib >= 0) {               // both ends in the tile: apply the reaction too (LDS subtract)
         unsigned long long* pb = (unsigned long long*)((char*)acc + __umul24((unsigned)ib, 24u));
-        atomicAdd(pb, (unsigned long long)(-fx));
-        atomicAdd(pb + 1, (unsigned long long)(-fy));
-        atomicAdd(pb + 2, (unsigned long long)(-fz));
+        __hip_atomic_fetch_sub(pb, (unsigned long long)fx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_sub(pb + 1, (unsigned long long)fy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_sub(pb + 2, (unsigned long long)fz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
