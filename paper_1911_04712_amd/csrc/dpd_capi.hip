@@ -99,6 +99,7 @@ Layout make_layout(int64_t n, int64_t nc)
     L.force = take(nn * sizeof(float4));
     L.keyslot = take(nn * sizeof(int2));
     L.perm = take(nn * sizeof(int));
+    L.cellof = take(nn * sizeof(int));
     L.out = take(nn * 3 * sizeof(float));
     L.count = take((size_t)nc * sizeof(int));
     L.cell_start = take((size_t)(nc + 1) * sizeof(int));
@@ -368,6 +369,7 @@ int push_desc(dpd_box_s* b)
     d.force = (float4*)(w + L.force);
     d.keyslot = (int2*)(w + L.keyslot);
     d.perm = (int*)(w + L.perm);
+    d.cellof = (int*)(w + L.cellof);
     d.count = (int*)(w + L.count);
     d.cell_start = (int*)(w + L.cell_start);
     d.bsum = (int*)(w + L.bsum);

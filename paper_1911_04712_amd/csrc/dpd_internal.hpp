@@ -154,6 +154,7 @@ struct BoxDesc {
     float4* force;             // total force of the last step, cell order
     int2* keyslot;             // (cell, arrival slot) of pos_a
     int* perm;                 // cell order -> index into pos_a (arrival order)
+    int* cellof;               // cell order -> cell of that position
     int* count;                // particles per cell (zeroed by the scan)
     int* cell_start;           // nc + 1
     int* bsum;                 // particles per kSubChunk cells (zeroed by the scatter)
@@ -197,6 +198,7 @@ struct Layout {
     size_t force;             // float4[n]  total force of the last step, cell order
     size_t keyslot;           // int2[n]    (cell, arrival slot) of pos_a
     size_t perm;              // int[n]     cell order -> index into pos_a (unstable)
+    size_t cellof;            // int[n]     cell order -> cell
     size_t out;               // float[3n]  staging of reads and writes in id order
     size_t count;             // int[nc]    particles per cell
     size_t cell_start;        // int[nc+1]

@@ -9,8 +9,10 @@
 //              a state load, k_keys and k_sub_sums);
 //   scan    -- each block scans its chunk after a block-wide reduction of the
 //              chunk sums before it, giving cell_start; counters are zeroed;
-//   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary);
-//              the sub-chunk counts are zeroed for the next step;
+//   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary),
+//              and the cell of that position beside it (so the gather looks up
+//              the cell's bounds while it loads the particle); the sub-chunk
+//              counts are zeroed for the next step;
 //   gather  -- each particle's final place is cell_start + its rank by
 //              previous index among the cell's members, so the order inside a
 //              cell is the previous array order whatever the atomics did.
@@ -398,7 +400,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BoxDesc* __restrict__ 
     if (i < d.nsub) d.bsum[i] = 0;               // the scan has read them; the next keys add to zero
     if (i >= d.n) return;
     const int2 ks = d.keyslot[i];
-    d.perm[d.cell_start[ks.x] + ks.y] = i;
+    const int p = d.cell_start[ks.x] + ks.y;
+    d.perm[p] = i;
+    d.cellof[p] = ks.x;
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ desc, const int* __restrict__ pre,
@@ -412,9 +416,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const BoxDesc* __restrict__ d
     const int p = lb * kBlock + threadIdx.x;
     if (p >= d.n) return;
     const int* __restrict__ perm = d.perm;
-    const int i = perm[p];
+    const int i = perm[p], c = d.cellof[p];
     const float4 x = d.pos_a[i], v = d.vel_a[i];     // in flight during the rank search
-    const int c = d.keyslot[i].x;
     const int s = d.cell_start[c], e = d.cell_start[c + 1];
     // the first eight members in one round of independent loads (a cell
     // rarely holds more), then the rest one by one
