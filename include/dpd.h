@@ -239,7 +239,9 @@ int dpd_get_frozen(dpd_box box, uint8_t* frozen_host);
 int dpd_wall_sdf(dpd_box box, float* sdf_host);
 
 /* Cell-tile shape of the LDS pair-force kernel: tile[3] edges in cells
- * (each 1..16), or {0, 0, 0} for the default chosen from the density.
+ * (each 1..16), or {0, 0, 0} for the default: from a short list per
+ * density class (rho <= 4.5 or above), the first shape that gives at least
+ * 512 tiles and fits a CU's LDS, each with its own workgroup size.
  * Results do not depend on the tile shape (bitwise). */
 int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 
@@ -247,9 +249,10 @@ int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 int dpd_get_tile(dpd_box box, int32_t tile[3]);
 
 /* Workgroup size of the LDS pair-force kernel: 256, 512 or 1024 threads
- * (4, 8 or 16 waves sharing one tile), or 0 for the default 512.  Results
- * do not depend on it (bitwise).  DPD_EINVAL for other values, or if the
- * current tile would then need more LDS than a CU has. */
+ * (4, 8 or 16 waves sharing one tile), or 0 for the default (the default
+ * tile's own size, 512 with a tile set by dpd_set_tile).  Results do not
+ * depend on it (bitwise).  DPD_EINVAL for other values, or if the current
+ * tile would then need more LDS than a CU has. */
 int dpd_set_force_threads(dpd_box box, int32_t threads);
 
 /* The workgroup size in use. */
