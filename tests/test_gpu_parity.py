@@ -564,6 +564,31 @@ def test_error_paths():
     b.close()
 
 
+def test_pair_force_beyond_the_fixed_point_range_is_reported():
+    """Pair forces are summed as 64-bit fixed point, 2^31 units per force
+    unit, with a range of 2^19 per pair (include/dpd.h, DPD_ENONFINITE).  Two
+    particles 0.5 apart closing at relative speed 2V feel a dissipative
+    force of 2 gamma w^2 V = 2.25 V: at V = 1e4 it is summed (and matches the
+    FP64 oracle), at V = 1e6 it is beyond the range, adds nothing and is
+    reported."""
+    cells = (4, 4, 4)
+    pos = np.array([[1.25, 2.0, 2.0], [1.75, 2.0, 2.0]], np.float32)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=1e-6)
+    ids = np.arange(2, dtype=np.uint32)
+    for v, reported in [(1e4, False), (1e6, True)]:
+        vel = np.array([[v, 0.0, 0.0], [-v, 0.0, 0.0]], np.float32)
+        b = _box(cells, pos, vel, params, 5)
+        b.step(1)
+        st = b.stats(allow_nonfinite=True)
+        assert st["nonfinite"] == (1 if reported else 0), v
+        if not reported:
+            f_gpu = b.read(dpd.FORCE)
+            assert f_gpu[0, 0] < -2.0e4 and f_gpu[1, 0] == -f_gpu[0, 0]
+            f_orc, s_orc, _ = oracle.forces(pos, vel, ids, cells, _orc_params(params), step=0, seed=5)
+            _force_check(f_gpu, f_orc, s_orc, f"closing pair v={v:g}")
+        b.close()
+
+
 def test_empty_and_single_particle_boxes():
     b = dpd.Box((3, 3, 3), 0, params=dpd.make_params(), seed=0)
     b.set_state(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32))
