@@ -263,7 +263,9 @@ int dpd_get_force_threads(dpd_box box, int32_t* threads);
  * workgroup (those whose LDS fits a CU), `reps` launches each with HIP
  * events on the box stream, keep the fastest pair and report the tile in
  * tile_out (the workgroup size through dpd_get_force_threads) and *ms_out
- * (mean ms per force evaluation; may be NULL).  The
+ * (mean ms per launch; may be NULL).  A box without walls is timed with the
+ * kernel its steps run, forces with the kick-drift fused; the state, the
+ * diagnostics and the flow profile are put back afterwards.  The
  * state does not advance (the box is left holding its cell list, as after
  * dpd_build_cells) and, since results do not depend on the tile, no result
  * changes.  Synchronises. */

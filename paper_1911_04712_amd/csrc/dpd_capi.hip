@@ -1182,6 +1182,25 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     const auto& cand = kTuneCand;
     const int saved[3] = {b->tile_req[0], b->tile_req[1], b->tile_req[2]};
     const int saved_threads = b->threads_req;
+    // A box whose steps fuse the kick-drift into the force kernel is timed
+    // with that kernel: its per-tile write-out costs more on small tiles than
+    // the forces alone show.  The fused launches write the next state and
+    // add to the cell counters, the reductions and the flow profile, so the
+    // state is put back afterwards: the cell-ordered copy (pos_b, vel_b)
+    // becomes the state again (a reordering the stable binning undoes), the
+    // counters start from zero, and the diagnostics and profile bins are
+    // restored from host copies.
+    const bool fused = b->lp.fuse;
+    const dpd::BoxDesc& dd = b->hd;
+    const size_t prof_bytes = (size_t)b->params.profile_bins * 2 * sizeof(long long);
+    dpd::DevStats st_keep{};
+    std::vector<long long> prof_keep(prof_bytes / sizeof(long long));
+    if (fused) {
+        HIPCHK(hipMemcpyAsync(&st_keep, dd.st, sizeof st_keep, hipMemcpyDeviceToHost, b->stream));
+        if (prof_bytes)
+            HIPCHK(hipMemcpyAsync(prof_keep.data(), dd.profile, prof_bytes, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1197,9 +1216,9 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
         rc = push_desc(b);
         if (rc) break;
         float ms = 0.0f;
-        hipError_t e = dpd::launch_force(b->lp, b->stream, false);          // warm-up
+        hipError_t e = dpd::launch_force(b->lp, b->stream, fused);          // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream, false);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(b->lp, b->stream, fused);
         if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1216,6 +1235,17 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (fused) {
+        const size_t rows = (size_t)b->n * sizeof(float4);
+        HIPCHK(hipMemcpyAsync(dd.pos_a, dd.pos_b, rows, hipMemcpyDeviceToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(dd.vel_a, dd.vel_b, rows, hipMemcpyDeviceToDevice, b->stream));
+        HIPCHK(dpd::launch_fill_i32(dd.count, 0, b->nc, b->stream));
+        HIPCHK(dpd::launch_fill_i32(dd.bsum, 0, dd.nsub, b->stream));
+        HIPCHK(hipMemcpyAsync(dd.st, &st_keep, sizeof st_keep, hipMemcpyHostToDevice, b->stream));
+        if (prof_bytes)
+            HIPCHK(hipMemcpyAsync(dd.profile, prof_keep.data(), prof_bytes, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
     const bool won = rc == DPD_OK && bt[0] > 0;
     for (int k = 0; k < 3; ++k) b->tile_req[k] = won ? bt[k] : saved[k];
     b->threads_req = won ? bthreads : saved_threads;
