@@ -242,7 +242,9 @@ int dpd_wall_sdf(dpd_box box, float* sdf_host);
  * (each 1..16), or {0, 0, 0} for the default: from a short list per
  * density class (rho <= 4.5 or above), the first shape that gives at least
  * 512 tiles and fits a CU's LDS, each with its own workgroup size.
- * Results do not depend on the tile shape (bitwise). */
+ * Positions, velocities and forces do not depend on the tile shape
+ * (bitwise); the FP64 diagnostics are folded per tile, in a fixed order, so
+ * their last bits follow the tile. */
 int dpd_set_tile(dpd_box box, const int32_t tile[3]);
 
 /* The tile shape in use (after clamping to the box). */
@@ -267,8 +269,8 @@ int dpd_get_force_threads(dpd_box box, int32_t* threads);
  * kernel its steps run, forces with the kick-drift fused; the state, the
  * diagnostics and the flow profile are put back afterwards.  The
  * state does not advance (the box is left holding its cell list, as after
- * dpd_build_cells) and, since results do not depend on the tile, no result
- * changes.  Synchronises. */
+ * dpd_build_cells) and, since the trajectory does not depend on the tile,
+ * no position, velocity or force changes.  Synchronises. */
 int dpd_tune_tile(dpd_box box, int32_t reps, int32_t tile_out[3], double* ms_out);
 
 /* Autotuner cache: a JSON file (path NULL or "" turns the cache off) that
@@ -280,8 +282,9 @@ int dpd_tune_tile(dpd_box box, int32_t reps, int32_t tile_out[3], double* ms_out
  * applies the stored tile and workgroup size (if they still fit a CU's LDS)
  * without timing and reports the stored ms; a miss times as usual and adds
  * the winner to the file (rewritten whole; an unwritable place keeps the
- * entries in memory only).  Process-wide; thread-safe.  Results never depend
- * on the tile, so the cache changes speed only. */
+ * entries in memory only).  Process-wide; thread-safe.  Trajectories never
+ * depend on the tile, so the cache changes speed (and the last bits of the
+ * FP64 diagnostics) only. */
 int dpd_set_tune_cache(const char* path);
 
 /* Set the 64-bit seed of the random term. */
@@ -433,8 +436,9 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
  * winning workgroup size (one launch has one; a batch runs with its first
  * box's); *ms_out (may be NULL) the mean ms per batched force evaluation.  Boxes must have params, seed and
  * state and must not hold a bare cell list; afterwards every box holds its
- * cell list (dpd_batch_step then starts from it).  No result changes: the
- * state does not advance and results do not depend on the tile.
+ * cell list (dpd_batch_step then starts from it).  No position, velocity or
+ * force changes: the state does not advance and the trajectory does not
+ * depend on the tile.
  * Synchronises. */
 int dpd_batch_tune(dpd_batch batch, int32_t reps, int32_t tile_out[3], double* ms_out);
 

@@ -162,20 +162,35 @@ def test_batch_tuner_changes_no_bits():
 
 
 def test_autotuner_picks_a_tile_and_changes_no_bits():
+    # the tuner times the fused kernel (forces and kick-drift), whose launches
+    # write the next state and add to the reductions and the flow profile: it
+    # puts all of them back, so the diagnostics and the profile stay the same
+    # (the FP64 reductions are folded per tile, so their rounding follows the
+    # tile: the reference takes the tuned tile at the same step)
     cells = (20, 16, 12)
     pos, vel = inputs.uniform_state(cells, density=3.0, seed=41)
-    ref = dpd.Box(cells, len(pos), params=dpd.make_params(), seed=41)
-    ref.set_state(pos, vel)
-    ref.step(12)
-    tuned = dpd.Box(cells, len(pos), params=dpd.make_params(), seed=41)
+    params = dpd.make_params(body_f=0.05, profile_bins=16)
+    tuned = dpd.Box(cells, len(pos), params=params, seed=41)
     tuned.set_state(pos, vel)
     tuned.step(5)
     tile, ms = tuned.tune_tile(reps=3)
     assert all(1 <= t <= 16 for t in tile) and ms > 0
     assert tuned.get_tile() == tile
     tuned.step(7)
+    ref = dpd.Box(cells, len(pos), params=params, seed=41)
+    ref.set_state(pos, vel)
+    ref.step(5)
+    ref.set_tile(tile)
+    ref.set_force_threads(tuned.get_force_threads())
+    ref.step(7)
     for what in (dpd.POS, dpd.VEL, dpd.FORCE):
         np.testing.assert_array_equal(tuned.read(what), ref.read(what))
+    st_t, st_r = tuned.stats(), ref.stats()
+    assert st_t.keys() == st_r.keys()
+    for k in st_r:
+        np.testing.assert_array_equal(st_t[k], st_r[k], err_msg=k)
+    for a, b in zip(tuned.profile(), ref.profile()):
+        np.testing.assert_array_equal(a, b)
     ref.close()
     tuned.close()
 
