@@ -434,7 +434,10 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
  * box); keeps the fastest.  tile_out receives the uniform tile, or
  * {0, 0, 0} when the boxes' own tiles were fastest, and every box the
  * winning workgroup size (one launch has one; a batch runs with its first
- * box's); *ms_out (may be NULL) the mean ms per batched force evaluation.  Boxes must have params, seed and
+ * box's); *ms_out (may be NULL) the mean ms per batched launch.  A batch
+ * without walls is timed with the kernel its steps run (forces with the
+ * kick-drift fused); every box's state, diagnostics and flow profile are put
+ * back afterwards.  Boxes must have params, seed and
  * state and must not hold a bare cell list; afterwards every box holds its
  * cell list (dpd_batch_step then starts from it).  No position, velocity or
  * force changes: the state does not advance and the trajectory does not

@@ -1147,6 +1147,50 @@ int dpd_time_force(dpd_box b, int32_t reps, double* ms_out)
     return DPD_OK;
 }
 
+namespace {
+
+// Timing the force kernel with the kick-drift fused (the kernel a box
+// without walls steps with) writes the next state and adds to the cell
+// counters, the reductions and the flow profile.  The tuners keep the
+// diagnostics and profile bins on the host before such launches and put
+// everything back after them: the cell-ordered copy (pos_b, vel_b) becomes
+// the state again (a reordering the stable binning undoes), and the counters
+// start from zero as after a binning.
+struct FusedKeep {
+    dpd::DevStats st{};
+    std::vector<long long> prof;
+};
+
+int fused_keep(const dpd_box_s* b, FusedKeep& k)
+{
+    const dpd::BoxDesc& d = b->hd;
+    k.prof.assign((size_t)b->params.profile_bins * 2, 0);
+    HIPCHK(hipMemcpyAsync(&k.st, d.st, sizeof k.st, hipMemcpyDeviceToHost, b->stream));
+    if (!k.prof.empty())
+        HIPCHK(hipMemcpyAsync(k.prof.data(), d.profile, k.prof.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                              b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return DPD_OK;
+}
+
+int fused_restore(const dpd_box_s* b, const FusedKeep& k)
+{
+    const dpd::BoxDesc& d = b->hd;
+    const size_t rows = (size_t)b->n * sizeof(float4);
+    HIPCHK(hipMemcpyAsync(d.pos_a, d.pos_b, rows, hipMemcpyDeviceToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(d.vel_a, d.vel_b, rows, hipMemcpyDeviceToDevice, b->stream));
+    HIPCHK(dpd::launch_fill_i32(d.count, 0, b->nc, b->stream));
+    HIPCHK(dpd::launch_fill_i32(d.bsum, 0, d.nsub, b->stream));
+    HIPCHK(hipMemcpyAsync(d.st, &k.st, sizeof k.st, hipMemcpyHostToDevice, b->stream));
+    if (!k.prof.empty())
+        HIPCHK(hipMemcpyAsync(d.profile, k.prof.data(), k.prof.size() * sizeof(long long), hipMemcpyHostToDevice,
+                              b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return DPD_OK;
+}
+
+}  // namespace
+
 int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
 {
     if (!b || !tile_out) return fail(DPD_EINVAL, "dpd_tune_tile: null argument");
@@ -1184,22 +1228,12 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     const int saved_threads = b->threads_req;
     // A box whose steps fuse the kick-drift into the force kernel is timed
     // with that kernel: its per-tile write-out costs more on small tiles than
-    // the forces alone show.  The fused launches write the next state and
-    // add to the cell counters, the reductions and the flow profile, so the
-    // state is put back afterwards: the cell-ordered copy (pos_b, vel_b)
-    // becomes the state again (a reordering the stable binning undoes), the
-    // counters start from zero, and the diagnostics and profile bins are
-    // restored from host copies.
+    // the forces alone show.
     const bool fused = b->lp.fuse;
-    const dpd::BoxDesc& dd = b->hd;
-    const size_t prof_bytes = (size_t)b->params.profile_bins * 2 * sizeof(long long);
-    dpd::DevStats st_keep{};
-    std::vector<long long> prof_keep(prof_bytes / sizeof(long long));
+    FusedKeep keep;
     if (fused) {
-        HIPCHK(hipMemcpyAsync(&st_keep, dd.st, sizeof st_keep, hipMemcpyDeviceToHost, b->stream));
-        if (prof_bytes)
-            HIPCHK(hipMemcpyAsync(prof_keep.data(), dd.profile, prof_bytes, hipMemcpyDeviceToHost, b->stream));
-        HIPCHK(hipStreamSynchronize(b->stream));
+        const int rk = fused_keep(b, keep);
+        if (rk) return rk;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
@@ -1236,15 +1270,8 @@ int dpd_tune_tile(dpd_box b, int32_t reps, int32_t tile_out[3], double* ms_out)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (fused) {
-        const size_t rows = (size_t)b->n * sizeof(float4);
-        HIPCHK(hipMemcpyAsync(dd.pos_a, dd.pos_b, rows, hipMemcpyDeviceToDevice, b->stream));
-        HIPCHK(hipMemcpyAsync(dd.vel_a, dd.vel_b, rows, hipMemcpyDeviceToDevice, b->stream));
-        HIPCHK(dpd::launch_fill_i32(dd.count, 0, b->nc, b->stream));
-        HIPCHK(dpd::launch_fill_i32(dd.bsum, 0, dd.nsub, b->stream));
-        HIPCHK(hipMemcpyAsync(dd.st, &st_keep, sizeof st_keep, hipMemcpyHostToDevice, b->stream));
-        if (prof_bytes)
-            HIPCHK(hipMemcpyAsync(dd.profile, prof_keep.data(), prof_bytes, hipMemcpyHostToDevice, b->stream));
-        HIPCHK(hipStreamSynchronize(b->stream));
+        const int rr = fused_restore(b, keep);
+        if (rr) return rr;
     }
     const bool won = rc == DPD_OK && bt[0] > 0;
     for (int k = 0; k < 3; ++k) b->tile_req[k] = won ? bt[k] : saved[k];
@@ -1637,6 +1664,15 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
             return DPD_OK;
         }
     }
+    // batches of boxes without walls step with the fused kernel: timed with
+    // it, every box's state and diagnostics put back afterwards
+    const bool fused = bt->lp.fuse;
+    std::vector<FusedKeep> keep(fused ? bt->boxes.size() : 0);
+    if (fused) HIPCHK(hipStreamSynchronize(bt->stream));   // the binning above (and its fold) is done
+    for (size_t i = 0; i < keep.size(); ++i) {
+        const int rk = fused_keep(bt->boxes[i], keep[i]);
+        if (rk) return rk;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1663,9 +1699,9 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
         if (rc == DPD_OK) rc = batch_refresh(bt);
         if (rc) break;
         float ms = 0.0f;
-        hipError_t e = dpd::launch_force(bt->lp, bt->stream, false);     // warm-up
+        hipError_t e = dpd::launch_force(bt->lp, bt->stream, fused);     // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, bt->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(bt->lp, bt->stream, false);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = dpd::launch_force(bt->lp, bt->stream, fused);
         if (e == hipSuccess) e = hipEventRecord(e1, bt->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1683,6 +1719,13 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (fused) {
+        HIPCHK(hipStreamSynchronize(bt->stream));
+        for (size_t i = 0; i < keep.size(); ++i) {
+            const int rr = fused_restore(bt->boxes[i], keep[i]);
+            if (rr) return rr;
+        }
+    }
     // apply the winner (or restore the boxes' own tiles)
     int rc2 = DPD_OK;
     for (size_t i = 0; i < bt->boxes.size() && rc2 == DPD_OK; ++i) {

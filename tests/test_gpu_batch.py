@@ -128,15 +128,18 @@ def test_batch_errors():
 
 
 def test_batch_tuner_changes_no_bits():
+    # the batch tuner times the fused kernel and puts every box's state,
+    # counters, diagnostics and (fixed-point, so tile-independent) flow
+    # profile back
     cells = [(9, 8, 8), (16, 12, 10), (6, 6, 6), (24, 9, 11)]
-    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01)
+    params = dpd.make_params(a=25.0, gamma=4.5, kT=1.0, dt=0.01, body_f=0.05, profile_bins=6)
     states = [inputs.uniform_state(c, density=3.0, seed=60 + k) for k, c in enumerate(cells)]
     alone = []
     for k, (c, (p, v)) in enumerate(zip(cells, states)):
         b = dpd.Box(c, len(p), params=params, seed=60 + k)
         b.set_state(p, v)
         b.step(9)
-        alone.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE)))
+        alone.append((b.read(dpd.POS), b.read(dpd.VEL), b.read(dpd.FORCE), b.profile(), b.stats()["nsamples"]))
         b.close()
     boxes = []
     for k, (c, (p, v)) in enumerate(zip(cells, states)):
@@ -152,10 +155,12 @@ def test_batch_tuner_changes_no_bits():
                    for b, b_cells in zip(boxes, cells))
     batch.step(5)
     for b, ref in zip(boxes, alone):
-        assert b.stats()["step"] == 9
+        assert b.stats()["step"] == 9 and b.stats()["nsamples"] == ref[4]
         np.testing.assert_array_equal(b.read(dpd.POS), ref[0])
         np.testing.assert_array_equal(b.read(dpd.VEL), ref[1])
         np.testing.assert_array_equal(b.read(dpd.FORCE), ref[2])
+        for got, want in zip(b.profile(), ref[3]):
+            np.testing.assert_array_equal(got, want)
     batch.close()
     for b in boxes:
         b.close()
