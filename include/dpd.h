@@ -265,8 +265,9 @@ int dpd_get_force_threads(dpd_box box, int32_t* threads);
  * workgroup (those whose LDS fits a CU), `reps` launches each with HIP
  * events on the box stream, keep the fastest pair and report the tile in
  * tile_out (the workgroup size through dpd_get_force_threads) and *ms_out
- * (mean ms per launch; may be NULL).  A box without walls is timed with the
- * kernel its steps run, forces with the kick-drift fused; the state, the
+ * (mean ms per launch; may be NULL).  The box is timed with the kernel its
+ * steps run, forces with the kick-drift fused (with the walls' conditions
+ * when it has walls); the state, the
  * diagnostics and the flow profile are put back afterwards.  The
  * state does not advance (the box is left holding its cell list, as after
  * dpd_build_cells) and, since the trajectory does not depend on the tile,
@@ -363,9 +364,9 @@ int dpd_destroy(dpd_box box);
 
 /* Run nsteps >= 1 steps eagerly (no graph) and return the mean device time
  * per step of each stage in ms_out[4]: binning (scan, scatter, gather),
- * pair forces (with the kick-drift when it is fused into the force kernel:
- * boxes without walls), virial (0 unless DPD_FLAG_VIRIAL), integrate (0 when
- * fused).  Each stage is timed by events that its first kernel records as it
+ * pair forces (with the kick-drift, which is fused into the force kernel
+ * except on the reference force path), virial (0 unless DPD_FLAG_VIRIAL),
+ * integrate (0 when fused).  Each stage is timed by events that its first kernel records as it
  * starts and its last as it ends (hipExtLaunchKernel), so the times are the
  * kernels' own, from the first one's start to the last one's end.  The fold
  * of the reductions, which a graph runs inside the next step's gather, runs
@@ -434,9 +435,9 @@ int dpd_batch_create(const dpd_box* boxes, int32_t nboxes, void* dev_ws, size_t 
  * box); keeps the fastest.  tile_out receives the uniform tile, or
  * {0, 0, 0} when the boxes' own tiles were fastest, and every box the
  * winning workgroup size (one launch has one; a batch runs with its first
- * box's); *ms_out (may be NULL) the mean ms per batched launch.  A batch
- * without walls is timed with the kernel its steps run (forces with the
- * kick-drift fused); every box's state, diagnostics and flow profile are put
+ * box's); *ms_out (may be NULL) the mean ms per batched launch.  The batch
+ * is timed with the kernel its steps run (forces with the kick-drift fused);
+ * every box's state, diagnostics and flow profile are put
  * back afterwards.  Boxes must have params, seed and
  * state and must not hold a bare cell list; afterwards every box holds its
  * cell list (dpd_batch_step then starts from it).  No position, velocity or

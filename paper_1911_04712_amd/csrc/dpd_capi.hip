@@ -406,7 +406,7 @@ int push_desc(dpd_box_s* b)
     // forces: every table entry is then that one pair)
     b->lp.species = d.fc.ntypes > 1 || b->max_type > 0;
     b->lp.walls = d.sc.wall_kind != 0 || b->n_frozen > 0;
-    b->lp.fuse = !b->lp.walls && !b->lp.reference_force;
+    b->lp.fuse = !b->lp.reference_force;      // the reference force path has no tile kernel to fuse into
     // a captured graph holds the kernel choice and the launch shapes
     if (old.lds_force != b->lp.lds_force || old.any_virial != b->lp.any_virial ||
         old.reference_force != b->lp.reference_force || old.species != b->lp.species || old.walls != b->lp.walls ||
@@ -1149,8 +1149,8 @@ int dpd_time_force(dpd_box b, int32_t reps, double* ms_out)
 
 namespace {
 
-// Timing the force kernel with the kick-drift fused (the kernel a box
-// without walls steps with) writes the next state and adds to the cell
+// Timing the force kernel with the kick-drift fused (the kernel every box
+// steps with, the reference force path aside) writes the next state and adds to the cell
 // counters, the reductions and the flow profile.  The tuners keep the
 // diagnostics and profile bins on the host before such launches and put
 // everything back after them: the cell-ordered copy (pos_b, vel_b) becomes
@@ -1505,7 +1505,7 @@ int batch_refresh(dpd_batch_s* bt)
             bt->pre[(size_t)k * (nb + 1) + i + 1] = bt->pre[(size_t)k * (nb + 1) + i] + dpd::box_work(h[i], k);
     }
     bool changed = bt->lp.lds_force != lds || bt->lp.any_virial != virial || bt->lp.species != species ||
-                   bt->lp.walls != walls || bt->lp.force_threads != threads || bt->lp.fuse != !walls;
+                   bt->lp.walls != walls || bt->lp.force_threads != threads || !bt->lp.fuse;
     for (int k = 0; k < dpd::kNumWork; ++k) {
         const int tot = bt->pre[(size_t)k * (nb + 1) + nb];
         changed |= bt->lp.total[k] != tot;
@@ -1520,7 +1520,7 @@ int batch_refresh(dpd_batch_s* bt)
     bt->lp.walls = walls;
     bt->lp.force_threads = threads;
     bt->lp.reference_force = false;     // reference boxes take the gather path inside the tile kernel
-    bt->lp.fuse = !walls;
+    bt->lp.fuse = true;
     if (changed) bt->graph_dirty = true;   // launch shape changed: capture again
     HIPCHK(dpd::force_tiled_prepare(lds));
     // the tables go through pinned memory, so the copies are queued behind
@@ -1664,8 +1664,8 @@ int dpd_batch_tune(dpd_batch bt, int32_t reps, int32_t tile_out[3], double* ms_o
             return DPD_OK;
         }
     }
-    // batches of boxes without walls step with the fused kernel: timed with
-    // it, every box's state and diagnostics put back afterwards
+    // batches step with the fused kernel: timed with it, every box's state
+    // and diagnostics put back afterwards
     const bool fused = bt->lp.fuse;
     std::vector<FusedKeep> keep(fused ? bt->boxes.size() : 0);
     if (fused) HIPCHK(hipStreamSynchronize(bt->stream));   // the binning above (and its fold) is done

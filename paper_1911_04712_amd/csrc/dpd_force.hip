@@ -311,7 +311,9 @@ __device__ __forceinline__ void flush_hit(unsigned e, bool live, const float4* s
 constexpr int kProfSlots = 64;  // flow-profile slabs one tile sums in LDS before its global atomics
 
 // Write-out of tile t: each tile particle's total force, once, in cell
-// order.  With kFuse the particle's kick-drift follows at once (Sec. 3.1,
+// order.  With kFuse (1; 2 for a launch with walls: frozen particles, the
+// bounce-back, the velocity's .w read whole from the cell-ordered state) the
+// particle's kick-drift follows at once (Sec. 3.1,
 // time-stepping step 5, done here because the force is final): the next
 // position and velocity go to pos_a / vel_a, its next cell and arrival slot
 // to keyslot and the cell counters, and the tile's FP64 sums (fixed order:
@@ -324,7 +326,7 @@ constexpr int kProfSlots = 64;  // flow-profile slabs one tile sums in LDS befor
 // x^n, stored velocity (w = species) and force.  scr is LDS the kernel no
 // longer uses (at least kProfSlots * 12 + waves * 40 bytes).  Every thread
 // of the workgroup calls it.
-template <bool kFuse, int kThreads, typename Src>
+template <int kFuse, int kThreads, typename Src>
 __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* rows, int nrows, int nt, int o_grad,
                                            unsigned char* scr, Src src)
 {
@@ -334,9 +336,9 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
     int* p_cnt = (int*)(scr + kProfSlots * 8);
     double* s_red = (double*)(scr + kProfSlots * 12);
     const StepConst& sc = d.sc;
-    const int nbins = kFuse ? sc.nbins : 0;
+    const int nbins = kFuse != 0 ? sc.nbins : 0;
     const int blo = nbins > 0 ? max(0, min((int)((float)o_grad * sc.grad_scale), nbins - 1)) : 0;
-    if constexpr (kFuse) {
+    if constexpr (kFuse != 0) {
         for (int k = tid; k < kProfSlots; k += kThreads) {
             p_sum[k] = 0;
             p_cnt[k] = 0;
@@ -351,7 +353,7 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
         const int ti = ti0 + lane;
         const bool live = ti < nt;
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f), v = x, f = x;
-        int g = 0;
+        int g = 0, wfull = 0;
         if (live) {
             int r = 0;
             for (int st = top; st > 0; st >>= 1)
@@ -361,9 +363,15 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
             g = rw.z + k;
             src(rw, k, x, v, f);
             d.force[g] = f;
+            if constexpr (kFuse == 2) wfull = reinterpret_cast<const int*>(d.vel_b)[4 * g + 3];   // species | frozen
         }
-        if constexpr (kFuse) {
-            const Kicked kk = kick_drift(x, v, f, sc);
+        if constexpr (kFuse != 0) {
+            const bool frozen = kFuse == 2 && (wfull & kFrozenBit) != 0;   // wall particles never move
+            Kicked kk;
+            if constexpr (kFuse == 2)
+                kk = kick_drift_walls(x, v, f, live, frozen, sc);
+            else
+                kk = kick_drift(x, v, f, sc);
             bad |= !kk.fin;
             esc |= kk.esc;
             const int c = live ? cell_of(kk.nx, kk.ny, kk.nz, sc.cells[0], sc.cells[1], sc.cells[2]) : -1;
@@ -371,9 +379,9 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
             chunk_add(c, live, d.bsum);
             if (live) {
                 d.pos_a[g] = make_float4(kk.nx, kk.ny, kk.nz, x.w);
-                d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, v.w);
+                d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, kFuse == 2 ? __int_as_float(wfull) : v.w);
             }
-            if (live && kk.fin) {
+            if (live && kk.fin && !frozen) {
                 add_partials(m, kk);
                 if (nbins > 0) {
                     const int b = profile_bin(x, sc);
@@ -392,7 +400,7 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
             if (live) d.keyslot[g] = make_int2(c, slot);
         }
     }
-    if constexpr (kFuse) {
+    if constexpr (kFuse != 0) {
         if (bad) atomicOr(&d.st->nonfinite, 1);
         if (esc) atomicOr(&d.st->escaped, 1);
 #pragma unroll
@@ -421,7 +429,7 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
 
 // 1024-thread workgroups: at most 64 VGPRs, so that two fit a CU (8 waves
 // per SIMD); the smaller ones fit their LDS-bound count of workgroups anyway
-template <bool kSp, int kThreads, bool kFuse>
+template <bool kSp, int kThreads, int kFuse>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThreads == 1024 ? 8 : 1))) void k_force_tiled(const BoxDesc* __restrict__ desc,
                                                              const int* __restrict__ pre, int nbox)
 {
@@ -529,7 +537,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
         // the write-out takes the particles in another order: the barrier
         // makes every force written above visible to the whole workgroup
         __syncthreads();
-        if constexpr (kFuse)
+        if constexpr (kFuse != 0)
             write_tile<kFuse, kThreads>(d, t, rows, nrows, nt, o_grad, scr,
                                         [&](const int4& rw, int k, float4& x, float4& v, float4& f) {
                                             const int g = rw.z + k;
@@ -828,7 +836,7 @@ TileConst make_tile_const(const int* cells, double rho, const int* tile, int thr
     return tc;
 }
 
-template <bool kSp, bool kFuse>
+template <bool kSp, int kFuse>
 static void launch_tiled(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     const dim3 grid(lp.total[kWTile]);
@@ -852,11 +860,14 @@ hipError_t launch_force(const LaunchPlan& lp, hipStream_t s, bool integrate, hip
         if (lp.total[kWPart] > 0)
             launch_timed(k_force_gather, dim3(lp.total[kWPart]), dim3(kBlock), 0, s, t0, t1, lp.desc, lp.pre, lp.nbox);
     } else if (lp.total[kWTile] > 0) {
-        const bool fuse = integrate && lp.fuse;
+        // 0: forces only; 1: the kick-drift fused; 2: fused, with walls
+        const int fuse = integrate && lp.fuse ? (lp.walls ? 2 : 1) : 0;
         if (lp.species)
-            fuse ? launch_tiled<true, true>(lp, s, t0, t1) : launch_tiled<true, false>(lp, s, t0, t1);
+            fuse == 2 ? launch_tiled<true, 2>(lp, s, t0, t1)
+                      : (fuse == 1 ? launch_tiled<true, 1>(lp, s, t0, t1) : launch_tiled<true, 0>(lp, s, t0, t1));
         else
-            fuse ? launch_tiled<false, true>(lp, s, t0, t1) : launch_tiled<false, false>(lp, s, t0, t1);
+            fuse == 2 ? launch_tiled<false, 2>(lp, s, t0, t1)
+                      : (fuse == 1 ? launch_tiled<false, 1>(lp, s, t0, t1) : launch_tiled<false, 0>(lp, s, t0, t1));
     }
     return hipGetLastError();
 }
@@ -865,12 +876,15 @@ hipError_t force_tiled_prepare(int lds_bytes)
 {
     if (lds_bytes <= 65536) return hipSuccess;
     const void* fns[] = {
-        (const void*)k_force_tiled<false, 256, false>, (const void*)k_force_tiled<false, 512, false>,
-        (const void*)k_force_tiled<false, 1024, false>, (const void*)k_force_tiled<true, 256, false>,
-        (const void*)k_force_tiled<true, 512, false>, (const void*)k_force_tiled<true, 1024, false>,
-        (const void*)k_force_tiled<false, 256, true>, (const void*)k_force_tiled<false, 512, true>,
-        (const void*)k_force_tiled<false, 1024, true>, (const void*)k_force_tiled<true, 256, true>,
-        (const void*)k_force_tiled<true, 512, true>, (const void*)k_force_tiled<true, 1024, true>};
+        (const void*)k_force_tiled<false, 256, 0>, (const void*)k_force_tiled<false, 512, 0>,
+        (const void*)k_force_tiled<false, 1024, 0>, (const void*)k_force_tiled<true, 256, 0>,
+        (const void*)k_force_tiled<true, 512, 0>, (const void*)k_force_tiled<true, 1024, 0>,
+        (const void*)k_force_tiled<false, 256, 1>, (const void*)k_force_tiled<false, 512, 1>,
+        (const void*)k_force_tiled<false, 1024, 1>, (const void*)k_force_tiled<true, 256, 1>,
+        (const void*)k_force_tiled<true, 512, 1>, (const void*)k_force_tiled<true, 1024, 1>,
+        (const void*)k_force_tiled<false, 256, 2>, (const void*)k_force_tiled<false, 512, 2>,
+        (const void*)k_force_tiled<false, 1024, 2>, (const void*)k_force_tiled<true, 256, 2>,
+        (const void*)k_force_tiled<true, 512, 2>, (const void*)k_force_tiled<true, 1024, 2>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return e;

@@ -183,11 +183,11 @@ struct LaunchPlan {
     int lds_force;             // dynamic LDS of the tile kernel (max over boxes)
     int force_threads;         // workgroup size of the tile kernel (every box's tc.threads)
     bool species;              // some box has several species: the tile kernel reads the pair table
-    bool walls;                // some box has walls or frozen particles: the wall integrate kernel
+    bool walls;                // some box has walls or frozen particles: the wall kick-drift
     bool any_virial;
     bool reference_force;      // single box flagged DPD_FLAG_REFERENCE_FORCE
     bool fuse;                 // the tile kernel integrates each particle once its force is final
-                               // (no walls and no frozen particles in the launch, tile kernel)
+                               // (every launch of the tile kernel; not the reference force path)
 };
 
 // Layout of a box inside its caller-provided workspace.  All offsets are
@@ -375,6 +375,90 @@ __device__ __forceinline__ Kicked kick_drift(float4 x, float4 v, float4 f, const
     k.nx = nx;
     k.ny = ny;
     k.nz = nz;
+    return k;
+}
+
+constexpr int kBounceIters = 24;        // bisection steps of the bounce-back: t to 2^-24 of the drift
+
+// Kick and drift of one particle of a box with walls (Sec. 3.1, time-stepping
+// step 5, with the walls' conditions): a frozen wall particle keeps its place
+// and velocity, or turns rigidly with its cylinder and takes the wall
+// velocity there; a fluid particle whose drift ends inside a wall goes back
+// to the last point of its drift on the fluid side (bisection on the
+// position grid) with its velocity reversed in the wall's frame.  Shared by
+// the integrate kernel and the force kernel's fused write-out, so both
+// compute the same bits.
+__device__ __forceinline__ Kicked kick_drift_walls(float4 x, float4 v, float4 f, bool live, bool frozen,
+                                                   const StepConst& sc)
+{
+    Kicked k;
+    k.vcx = fmaf(f.x, sc.half_dtm, v.x);
+    k.vcy = fmaf(f.y, sc.half_dtm, v.y);
+    k.vcz = fmaf(f.z, sc.half_dtm, v.z);
+    float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
+    if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
+    float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
+          nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
+    bool turned = false;
+    if (frozen && sc.wall_kind == 3) {
+        // a turning cylinder turns its frozen layer rigidly by omega dt
+        // about the axis (the particle takes the wall velocity at its
+        // new, grid-rounded position below)
+        float c1, c2;
+        const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
+        if (sc.omega[cyl] != 0.0f) {
+            const float cs = sc.rot[cyl][0], sn = sc.rot[cyl][1];
+            const float3 dd = from_axes(sc, fmaf(cs, c1, -sn * c2) - c1, fmaf(sn, c1, cs * c2) - c2);
+            nx = x.x + dd.x;
+            ny = x.y + dd.y;
+            nz = x.z + dd.z;
+            turned = true;
+        }
+    }
+    k.fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) && isfinite(nz);
+    if (!k.fin) {
+        nx = x.x; ny = x.y; nz = x.z;
+    }
+    k.esc = fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
+    nx = rintf(nx * sc.inv_q) * sc.q;
+    ny = rintf(ny * sc.inv_q) * sc.q;
+    nz = rintf(nz * sc.inv_q) * sc.q;
+    if (turned) {               // the same velocity dpd_set_frozen gives a particle there
+        const float3 u = wall_velocity(nx, ny, nz, sc);
+        vx = u.x; vy = u.y; vz = u.z;
+    }
+    if (sc.wall_kind != 0 && live && !frozen && k.fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
+        // bounce-back: bisection for the sdf's zero along the drift, every
+        // probe on the position grid; the particle goes to the last probe
+        // on the fluid side (the start, t = 0, if none) and its velocity is
+        // reversed in the frame of the wall: v -> 2 u_wall - v
+        const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
+        float lo = 0.0f, hi = 1.0f;
+        for (int it = 0; it < kBounceIters; ++it) {
+            const float mid = 0.5f * (lo + hi);
+            const bool in = wall_sdf(rintf(fmaf(mid, dx, x.x) * sc.inv_q) * sc.q,
+                                     rintf(fmaf(mid, dy, x.y) * sc.inv_q) * sc.q,
+                                     rintf(fmaf(mid, dz, x.z) * sc.inv_q) * sc.q, sc) > 0.0f;
+            lo = in ? lo : mid;
+            hi = in ? mid : hi;
+        }
+        nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
+        ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
+        nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
+        const float3 u = wall_velocity(nx, ny, nz, sc);           // reversal in the wall's frame
+        vx = fmaf(2.0f, u.x, -vx); vy = fmaf(2.0f, u.y, -vy); vz = fmaf(2.0f, u.z, -vz);
+    }
+    if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
+    if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
+    if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
+    if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
+        k.esc = true;
+        nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
+        ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
+        nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
+    }
+    k.nx = nx; k.ny = ny; k.nz = nz;
+    k.vx = vx; k.vy = vy; k.vz = vz;
     return k;
 }
 

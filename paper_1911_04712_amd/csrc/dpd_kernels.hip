@@ -517,7 +517,6 @@ hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hip
 // fused velocity-Verlet + next keys + FP64 reductions
 // ---------------------------------------------------------------------------
 constexpr int kLdsBins = 1024;
-constexpr int kBounceIters = 24;        // bisection steps of the bounce-back: t to 2^-24 of the drift
 
 // kWalls: some box of the launch has walls (bounce-back and frozen particles);
 // the plain instantiation keeps the register budget of the wall-free step.
@@ -561,73 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const BoxDesc* __restrict_
         if constexpr (!kWalls) {
             k = kick_drift(x, v, f, sc);
         } else {
-            k.vcx = fmaf(f.x, sc.half_dtm, v.x);
-            k.vcy = fmaf(f.y, sc.half_dtm, v.y);
-            k.vcz = fmaf(f.z, sc.half_dtm, v.z);
-            float vx = fmaf(f.x, sc.dtm, v.x), vy = fmaf(f.y, sc.dtm, v.y), vz = fmaf(f.z, sc.dtm, v.z);
-            if (frozen) { vx = v.x; vy = v.y; vz = v.z; }
-            float nx = frozen ? x.x : fmaf(vx, sc.dt, x.x), ny = frozen ? x.y : fmaf(vy, sc.dt, x.y),
-                  nz = frozen ? x.z : fmaf(vz, sc.dt, x.z);
-            bool turned = false;
-            if (frozen && sc.wall_kind == 3) {
-                // a turning cylinder turns its frozen layer rigidly by omega dt
-                // about the axis (the particle takes the wall velocity at its
-                // new, grid-rounded position below)
-                float c1, c2;
-                const int cyl = cylinder_of(x.x, x.y, x.z, sc, c1, c2);
-                if (sc.omega[cyl] != 0.0f) {
-                    const float cs = sc.rot[cyl][0], sn = sc.rot[cyl][1];
-                    const float3 dd = from_axes(sc, fmaf(cs, c1, -sn * c2) - c1, fmaf(sn, c1, cs * c2) - c2);
-                    nx = x.x + dd.x;
-                    ny = x.y + dd.y;
-                    nz = x.z + dd.z;
-                    turned = true;
-                }
-            }
-            k.fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(nx) && isfinite(ny) && isfinite(nz);
-            if (!k.fin) {
-                nx = x.x; ny = x.y; nz = x.z;
-            }
-            k.esc = fabsf(nx - x.x) >= 1.0f || fabsf(ny - x.y) >= 1.0f || fabsf(nz - x.z) >= 1.0f;
-            nx = rintf(nx * sc.inv_q) * sc.q;
-            ny = rintf(ny * sc.inv_q) * sc.q;
-            nz = rintf(nz * sc.inv_q) * sc.q;
-            if (turned) {               // the same velocity dpd_set_frozen gives a particle there
-                const float3 u = wall_velocity(nx, ny, nz, sc);
-                vx = u.x; vy = u.y; vz = u.z;
-            }
-            if (sc.wall_kind != 0 && live && !frozen && k.fin && wall_sdf(nx, ny, nz, sc) > 0.0f) {
-                // bounce-back: bisection for the sdf's zero along the drift, every
-                // probe on the position grid; the particle goes to the last probe
-                // on the fluid side (the start, t = 0, if none) and its velocity is
-                // reversed in the frame of the wall: v -> 2 u_wall - v
-                const float dx = nx - x.x, dy = ny - x.y, dz = nz - x.z;
-                float lo = 0.0f, hi = 1.0f;
-                for (int it = 0; it < kBounceIters; ++it) {
-                    const float mid = 0.5f * (lo + hi);
-                    const bool in = wall_sdf(rintf(fmaf(mid, dx, x.x) * sc.inv_q) * sc.q,
-                                             rintf(fmaf(mid, dy, x.y) * sc.inv_q) * sc.q,
-                                             rintf(fmaf(mid, dz, x.z) * sc.inv_q) * sc.q, sc) > 0.0f;
-                    lo = in ? lo : mid;
-                    hi = in ? mid : hi;
-                }
-                nx = rintf(fmaf(lo, dx, x.x) * sc.inv_q) * sc.q;
-                ny = rintf(fmaf(lo, dy, x.y) * sc.inv_q) * sc.q;
-                nz = rintf(fmaf(lo, dz, x.z) * sc.inv_q) * sc.q;
-                const float3 u = wall_velocity(nx, ny, nz, sc);           // reversal in the wall's frame
-                vx = fmaf(2.0f, u.x, -vx); vy = fmaf(2.0f, u.y, -vy); vz = fmaf(2.0f, u.z, -vz);
-            }
-            if (nx >= sc.L[0]) nx -= sc.L[0]; else if (nx < 0.0f) nx += sc.L[0];
-            if (ny >= sc.L[1]) ny -= sc.L[1]; else if (ny < 0.0f) ny += sc.L[1];
-            if (nz >= sc.L[2]) nz -= sc.L[2]; else if (nz < 0.0f) nz += sc.L[2];
-            if (!(nx >= 0.0f && nx < sc.L[0] && ny >= 0.0f && ny < sc.L[1] && nz >= 0.0f && nz < sc.L[2])) {
-                k.esc = true;
-                nx = fminf(fmaxf(nx, 0.0f), sc.L[0] - sc.q);
-                ny = fminf(fmaxf(ny, 0.0f), sc.L[1] - sc.q);
-                nz = fminf(fmaxf(nz, 0.0f), sc.L[2] - sc.q);
-            }
-            k.nx = nx; k.ny = ny; k.nz = nz;
-            k.vx = vx; k.vy = vy; k.vz = vz;
+            k = kick_drift_walls(x, v, f, live, frozen, sc);
         }
         bad |= !k.fin;
         esc |= k.esc;

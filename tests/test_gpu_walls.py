@@ -145,6 +145,71 @@ def test_walls_batch_equals_alone():
         b.close()
 
 
+def test_tuners_on_walled_boxes_change_no_bits():
+    """The tuners time the force kernel with the walls' kick-drift fused into
+    it (frozen layers turning with their cylinders, bounce-back) and put each
+    box's state, diagnostics and flow profile back: a tuned box steps to the
+    same bits as one given the tuned tile, and a tuned batch to the same
+    positions, velocities, forces and profile as its boxes alone."""
+    r_in, r_out = 2.5, 5.5
+    cyl = dpd.make_params(wall_kind=dpd.WALL_CYLINDERS, wall_h=r_out, wall_r_in=r_in, omega_in=-0.15,
+                          omega_out=0.2, dt=0.01, profile_bins=8)
+    pos, vel, frozen = walls.carve((6, 14, 14), 3.0, dpd.make_params(dt=0.01), dpd.WALL_CYLINDERS, r_out,
+                                   seed=69, equil_steps=200, wall_r_in=r_in)
+    made = [((6, 14, 14), pos, vel, frozen, cyl, 69)]
+    for kind, cells, h, seed in [(dpd.WALL_PIPE, (6, 11, 12), 4.0, 70), (dpd.WALL_PLATES, (7, 10, 6), 3.0, 71)]:
+        p, v, f, q = _walled(kind, cells, h, seed, kick=4.0, dt=0.01, profile_bins=8)
+        made.append((cells, p, v, f, q, seed))
+
+    def box(cells, pos, vel, frozen, p, seed):
+        b = dpd.Box(cells, len(pos), params=p, seed=seed)
+        b.set_state(pos, vel)
+        b.set_frozen(frozen)
+        return b
+
+    def same(b, ref):
+        for what in (dpd.POS, dpd.VEL, dpd.FORCE):
+            np.testing.assert_array_equal(b.read(what), ref.read(what))
+        for x, y in zip(b.profile(), ref.profile()):
+            np.testing.assert_array_equal(x, y)
+
+    for m in made:
+        _say(f"[walls tuner] box {m[0]} kind {m[4].wall_kind}")
+        tuned = box(*m)
+        tuned.step(4)
+        tile, ms = tuned.tune_tile(reps=2)
+        assert ms > 0 and tuned.get_tile() == tile
+        tuned.step(5)
+        ref = box(*m)
+        ref.step(4)
+        ref.set_tile(tile)
+        ref.set_force_threads(tuned.get_force_threads())
+        ref.step(5)
+        same(tuned, ref)
+        st_t, st_r = tuned.stats(), ref.stats()
+        for k in st_r:
+            np.testing.assert_array_equal(st_t[k], st_r[k], err_msg=k)
+        tuned.close()
+        ref.close()
+
+    _say("[walls tuner] batch")
+    alone = [box(*m) for m in made]
+    for b in alone:
+        b.step(9)
+    boxes = [box(*m) for m in made]
+    bt = dpd.Batch(boxes)
+    bt.step(4)
+    _, ms = bt.tune(reps=2)
+    assert ms > 0
+    bt.step(5)
+    for b, ref in zip(boxes, alone):
+        assert b.stats()["step"] == 9 and b.stats()["nsamples"] == ref.stats()["nsamples"]
+        same(b, ref)
+    bt.close()
+    for b in boxes + alone:
+        b.close()
+
+
 def test_pipe_flow_viscosity_groot_warren():
     """Table 1's Groot-Warren row (a = 25, gamma = 6.75, rho = 3, kT = 1,
     dt = 0.04: eta = 0.89-0.90 in the paper's pipe) through pipe flow,
