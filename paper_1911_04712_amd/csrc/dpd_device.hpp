@@ -19,6 +19,48 @@
 
 namespace dpd {
 
+// Global-memory view of a device pointer.  A box's arrays reach the kernels
+// as plain pointers inside its descriptor, which the compiler must treat as
+// generic and access with FLAT instructions.  A FLAT access also counts
+// against the LDS wait counter, so every later LDS wait of the wave (a
+// shuffle, a barrier) waits until the access is done, stores included.
+// Through the global view the compiler emits global_* instructions, which
+// only the vector-memory counter tracks.
+#define DPD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ DPD_GLOBAL T* gmem(T* p)
+{
+    return (DPD_GLOBAL T*)p;
+}
+
+// Stores of HIP's vector types through the global view (their assignment
+// operators are declared for generic memory only).
+__device__ __forceinline__ void gstore(float4* p, float4 v)
+{
+    typedef float __attribute__((ext_vector_type(4))) v4;
+    const v4 t = {v.x, v.y, v.z, v.w};
+    *(DPD_GLOBAL v4*)p = t;
+}
+__device__ __forceinline__ void gstore(int2* p, int2 v)
+{
+    typedef int __attribute__((ext_vector_type(2))) i2;
+    const i2 t = {v.x, v.y};
+    *(DPD_GLOBAL i2*)p = t;
+}
+
+// Device-scope relaxed atomics (what atomicAdd / atomicOr are) on global
+// memory.
+template <typename T>
+__device__ __forceinline__ T gatomic_add(T* p, T v)
+{
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T gatomic_or(T* p, T v)
+{
+    return __hip_atomic_fetch_or(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): round multipliers and
 // Weyl key increments.
 constexpr uint32_t kPhM0 = 0xD2511F53u;

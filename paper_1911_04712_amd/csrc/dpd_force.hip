@@ -34,12 +34,11 @@
 
 namespace dpd {
 
-// Load through the global address space (the pointers in a box descriptor
-// are generic; this lets the load use the global instructions).
+// Load through the global address space (see gmem).
 __device__ __forceinline__ float4 gload4(const float4* p, int i)
 {
     typedef float __attribute__((ext_vector_type(4))) v4;
-    const v4 t = ((const __attribute__((address_space(1))) v4*)p)[i];
+    const v4 t = ((const DPD_GLOBAL v4*)p)[i];
     return make_float4(t.x, t.y, t.z, t.w);
 }
 
@@ -165,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const BoxDesc* __restri
     const uint32_t step = (uint32_t)d.st->step;
     d.force[i] = d.fc.ntypes > 1 ? gather_force_one<true>(i, d.pos_b, d.vel_b, d.cell_start, d.fc, step, bad)
                                  : gather_force_one<false>(i, d.pos_b, d.vel_b, d.cell_start, d.fc, step, bad);
-    if (bad) atomicOr(&d.st->nonfinite, 1);
+    if (bad) gatomic_or(&d.st->nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +337,7 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
     const StepConst& sc = d.sc;
     const int nbins = kFuse != 0 ? sc.nbins : 0;
     const int blo = nbins > 0 ? max(0, min((int)((float)o_grad * sc.grad_scale), nbins - 1)) : 0;
-    if constexpr (kFuse != 0) {
+    if (nbins > 0) {                                    // uniform; 0 without kFuse
         for (int k = tid; k < kProfSlots; k += kThreads) {
             p_sum[k] = 0;
             p_cnt[k] = 0;
@@ -362,8 +361,8 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
             const int k = ti - rw.w;
             g = rw.z + k;
             src(rw, k, x, v, f);
-            d.force[g] = f;
-            if constexpr (kFuse == 2) wfull = reinterpret_cast<const int*>(d.vel_b)[4 * g + 3];   // species | frozen
+            gstore(d.force + g, f);
+            if constexpr (kFuse == 2) wfull = gmem(reinterpret_cast<const int*>(d.vel_b))[4 * g + 3];   // species | frozen
         }
         if constexpr (kFuse != 0) {
             const bool frozen = kFuse == 2 && (wfull & kFrozenBit) != 0;   // wall particles never move
@@ -378,8 +377,8 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
             const ArrivalTicket tk = arrival_issue(c, live, d.count);   // atomic in flight meanwhile
             chunk_add(c, live, d.bsum);
             if (live) {
-                d.pos_a[g] = make_float4(kk.nx, kk.ny, kk.nz, x.w);
-                d.vel_a[g] = make_float4(kk.vx, kk.vy, kk.vz, kFuse == 2 ? __int_as_float(wfull) : v.w);
+                gstore(d.pos_a + g, make_float4(kk.nx, kk.ny, kk.nz, x.w));
+                gstore(d.vel_a + g, make_float4(kk.vx, kk.vy, kk.vz, kFuse == 2 ? __int_as_float(wfull) : v.w));
             }
             if (live && kk.fin && !frozen) {
                 add_partials(m, kk);
@@ -391,38 +390,43 @@ __device__ __forceinline__ void write_tile(const BoxDesc& d, int t, const int4* 
                         atomicAdd((unsigned long long*)&p_sum[sl], (unsigned long long)q);
                         atomicAdd(&p_cnt[sl], 1);
                     } else {
-                        atomicAdd((unsigned long long*)&d.profile[2 * b], (unsigned long long)q);
-                        atomicAdd((unsigned long long*)&d.profile[2 * b + 1], 1ull);
+                        gatomic_add((unsigned long long*)&d.profile[2 * b], (unsigned long long)q);
+                        gatomic_add((unsigned long long*)&d.profile[2 * b + 1], 1ull);
                     }
                 }
             }
             const int slot = arrival_finish(tk, live);
-            if (live) d.keyslot[g] = make_int2(c, slot);
+            if (live) gstore(d.keyslot + g, make_int2(c, slot));
         }
     }
     if constexpr (kFuse != 0) {
-        if (bad) atomicOr(&d.st->nonfinite, 1);
-        if (esc) atomicOr(&d.st->escaped, 1);
+        if (bad) gatomic_or(&d.st->nonfinite, 1);
+        if (esc) gatomic_or(&d.st->escaped, 1);
+        // only the waves that took particles hold sums: the others' are +0.0,
+        // which leaves a sum started at +0.0 unchanged, so they are skipped
+        const int nwl = min(nw, (nt + 63) >> 6);
+        if (wave < nwl) {                               // wave-uniform
 #pragma unroll
-        for (int k = 0; k < kPartials; ++k) {
-            const double w = wave_sum(m[k]);
-            if (lane == 0) s_red[wave * kPartials + k] = w;
+            for (int k = 0; k < kPartials; ++k) {
+                const double w = wave_sum(m[k]);
+                if (lane == 0) s_red[wave * kPartials + k] = w;
+            }
         }
         __syncthreads();
         if (tid < kPartials) {
             double sum = 0.0;
-            for (int w = 0; w < nw; ++w) sum += s_red[w * kPartials + tid];
-            d.partials[(size_t)t * kPartials + tid] = sum;
+            for (int w = 0; w < nwl; ++w) sum += s_red[w * kPartials + tid];
+            gmem(d.partials)[(size_t)t * kPartials + tid] = sum;
         }
         if (nbins > 0)
             for (int k = tid; k < kProfSlots; k += kThreads)
                 if (p_cnt[k]) {
-                    atomicAdd((unsigned long long*)&d.profile[2 * (blo + k)], (unsigned long long)p_sum[k]);
-                    atomicAdd((unsigned long long*)&d.profile[2 * (blo + k) + 1], (unsigned long long)p_cnt[k]);
+                    gatomic_add((unsigned long long*)&d.profile[2 * (blo + k)], (unsigned long long)p_sum[k]);
+                    gatomic_add((unsigned long long*)&d.profile[2 * (blo + k) + 1], (unsigned long long)p_cnt[k]);
                 }
         if (t == 0 && tid == 0) {      // the fold adds up one partial per tile
-            d.st->fold_count = (unsigned)d.tc.ntiles;
-            d.st->fold_pending = 1;
+            gmem(&d.st->fold_count)[0] = (unsigned)d.tc.ntiles;
+            gmem(&d.st->fold_pending)[0] = 1;
         }
     }
 }
@@ -490,9 +494,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
         const int rr = small_div(lc, inv_s0);                  // staged row
         const int lz = small_div(rr, inv_s1), ly = rr - lz * S1, lx = lc - rr * S0;
         const int g = wrap_cell(o0 - 1 + lx, L0) + L0 * (wrap_cell(o1 - 1 + ly, L1) + L1 * wrap_cell(o2 - 1 + lz, L2));
-        const int gs = cell_start[g];
+        const int gs = gmem(cell_start)[g];
         cg[lc] = gs;
-        cst[lc] = cell_start[g + 1] - gs;
+        cst[lc] = gmem(cell_start)[g + 1] - gs;
     }
     __syncthreads();
     const int S = block_excl_scan(cst, ncs, s_scr);
@@ -531,9 +535,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
         for (int r = wave; r < nrows; r += nw) {
             const int4 rw = rows[r];
             for (int k = lane; k < rw.y; k += 64)
-                force[rw.z + k] = gather_force_one<kSp>(rw.z + k, pos, vel, cell_start, fc, step, bad);
+                gstore(force + rw.z + k, gather_force_one<kSp>(rw.z + k, pos, vel, cell_start, fc, step, bad));
         }
-        if (bad) atomicOr(nonfinite, 1);
+        if (bad) gatomic_or(nonfinite, 1);
         // the write-out takes the particles in another order: the barrier
         // makes every force written above visible to the whole workgroup
         __syncthreads();
@@ -778,7 +782,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
     }
     __builtin_amdgcn_wave_barrier();
     if (qt > 0) flush_hit<kSp>(q[lane], lane < qt, sp, sv, acc, step, pc, tab, bad);
-    if (bad) atomicOr(nonfinite, 1);
+    if (bad) gatomic_or(nonfinite, 1);
     __syncthreads();
 
     // 5. each tile particle's force is written once, in cell order (a tile

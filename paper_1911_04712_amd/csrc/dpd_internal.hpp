@@ -297,7 +297,7 @@ __device__ __forceinline__ ArrivalTicket arrival_issue(int key, bool valid, int*
     const int nlive = __popcll(live);                               // valid lanes are a prefix
     if (run_end > nlive) run_end = nlive;
     t.base = 0;
-    if (head) t.base = atomicAdd(&count[key], run_end - lane);
+    if (head) t.base = gatomic_add(&count[key], run_end - lane);
     return t;
 }
 
@@ -318,7 +318,7 @@ __device__ __forceinline__ void chunk_add(int key, bool valid, int* __restrict__
     const unsigned long long after = heads & ~upto;
     int run_end = after ? __ffsll((long long)after) - 1 : 64;
     if (run_end > nlive) run_end = nlive;
-    if (head) atomicAdd(&bsum[ck], run_end - lane);
+    if (head) gatomic_add(&bsum[ck], run_end - lane);
 }
 
 // Second half: every lane of the wave must call it.
