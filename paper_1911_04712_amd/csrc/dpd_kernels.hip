@@ -5,8 +5,9 @@
 // by cell) is a counting sort made stable and deterministic:
 //   keys    -- cell of each particle and an arrival slot from an atomic
 //              per-cell counter, plus particle counts per kSubChunk cells
-//              from a second counter (fused into the integrate kernel; after
-//              a state load, k_keys and k_sub_sums);
+//              from a second counter (fused into the kick-drift: the force
+//              kernel's write-out, or k_integrate on the reference force
+//              path; after a state load, k_keys and k_sub_sums);
 //   scan    -- each block scans its chunk after a block-wide reduction of the
 //              chunk sums before it, giving cell_start; counters are zeroed;
 //   scatter -- perm[cell_start + slot] = particle (slot order is arbitrary),
@@ -514,7 +515,9 @@ hipError_t launch_virial(const LaunchPlan& lp, hipStream_t s, hipEvent_t t0, hip
 }
 
 // ---------------------------------------------------------------------------
-// fused velocity-Verlet + next keys + FP64 reductions
+// fused velocity-Verlet + next keys + FP64 reductions, as a kernel of its own:
+// the step of the reference force path (every other step runs the same
+// kick-drift in the force kernel's write-out)
 // ---------------------------------------------------------------------------
 constexpr int kLdsBins = 1024;
 
