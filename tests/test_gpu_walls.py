@@ -210,6 +210,94 @@ def test_tuners_on_walled_boxes_change_no_bits():
         b.close()
 
 
+A2 = np.array([[25.0, 40.0], [40.0, 18.0]])
+G2 = np.array([[4.5, 9.0], [9.0, 3.0]])
+
+
+def test_walls_with_species_match_oracle_and_batch():
+    """Walls and several species together (the tile kernel's species and
+    walls instantiation): one step against the oracle, the reference gather
+    kernel bit-identical to the tile kernel, and a batch mixing walled,
+    species and walled-species boxes bit-identical to the boxes alone."""
+    cells, h, seed = (6, 11, 12), 4.0, 75
+    pos, vel, frozen, p = _walled(dpd.WALL_PIPE, cells, h, seed, kick=8.0, dt=0.01)
+    types = inputs.species_types(len(pos), [0.6, 0.4], seed=seed)
+
+    def box(flags=0):
+        q = dpd.make_params(wall_kind=p.wall_kind, wall_h=p.wall_h, flags=p.flags | flags, body_f=p.body_f,
+                            dt=p.dt)
+        b = dpd.Box(cells, len(pos), params=q, seed=seed)
+        b.set_state(pos, vel)
+        b.set_frozen(frozen)
+        b.set_species(A2, G2)
+        b.set_types(types)
+        return b
+
+    b = box()
+    b.step(1)
+    fg, xg, vg = b.read(dpd.FORCE), b.read(dpd.POS), b.read(dpd.VEL).astype(np.float64)
+    np.testing.assert_array_equal(b.get_types(), types)
+    np.testing.assert_array_equal(b.get_frozen(), frozen)
+    b.close()
+    q = oracle.with_walls(oracle.with_species(oracle.make_params(a=p.a, gamma=p.gamma, kT=p.kT, dt=p.dt,
+                                                                 body_f=p.body_f), types, A2, G2),
+                          p.wall_kind, p.wall_h, frozen.astype(np.uint8))
+    ids = np.arange(len(pos), dtype=np.uint32)
+    fo, so, _ = oracle.forces(pos, vel, ids, cells, q, 0, seed)
+    err = np.linalg.norm(fg.astype(np.float64) - fo, axis=1)
+    _say(f"[walls+species] max |df|/S = {np.max(err / so):.3e}")
+    assert np.all(err <= TOL_F * so)
+    # the step: velocities as in the one-step walls test, positions within
+    # two grid spacings, the pipe's frozen layer still
+    x, v = pos.astype(np.float64).copy(), vel.astype(np.float64).copy()
+    oracle.step(x, v, ids, cells, q, seed, 0, 1, want_diag=False)
+    tol_v = 0.01 * TOL_F * so[:, None] + 4 * np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(vg - v) <= tol_v)
+    dx = np.abs(xg.astype(np.float64) - x)
+    dx = np.minimum(dx, np.asarray(cells) - dx)
+    assert np.all(dx <= 2 * dpd.position_grid(cells) + 0.01 * np.abs(vg - v) + 1e-9)
+    np.testing.assert_array_equal(xg[frozen], pos[frozen])
+    br = box(dpd.FLAG_REFERENCE_FORCE)
+    br.step(1)
+    np.testing.assert_array_equal(br.read(dpd.FORCE), fg)
+    br.close()
+
+    # a batch of a walled-species box, a species box and a walled box
+    sp_pos, sp_vel = inputs.uniform_state((7, 6, 8), density=3.0, seed=76)
+    sp_types = inputs.species_types(len(sp_pos), [0.5, 0.5], seed=76)
+    w_pos, w_vel, w_frozen, w_p = _walled(dpd.WALL_PLATES, (7, 10, 6), 3.0, 77, dt=0.01)
+
+    def make(k):
+        if k == 0:
+            return box()
+        if k == 1:
+            bb = dpd.Box((7, 6, 8), len(sp_pos), params=dpd.make_params(dt=0.01), seed=76)
+            bb.set_state(sp_pos, sp_vel)
+            bb.set_species(A2, G2)
+            bb.set_types(sp_types)
+            return bb
+        bb = dpd.Box((7, 10, 6), len(w_pos), params=w_p, seed=77)
+        bb.set_state(w_pos, w_vel)
+        bb.set_frozen(w_frozen)
+        return bb
+
+    alone = []
+    for k in range(3):
+        bb = make(k)
+        bb.step(6)
+        alone.append((bb.read(dpd.POS), bb.read(dpd.VEL)))
+        bb.close()
+    boxes = [make(k) for k in range(3)]
+    bt = dpd.Batch(boxes)
+    bt.step(6)
+    for bb, ref in zip(boxes, alone):
+        np.testing.assert_array_equal(bb.read(dpd.POS), ref[0])
+        np.testing.assert_array_equal(bb.read(dpd.VEL), ref[1])
+    bt.close()
+    for bb in boxes:
+        bb.close()
+
+
 def test_pipe_flow_viscosity_groot_warren():
     """Table 1's Groot-Warren row (a = 25, gamma = 6.75, rho = 3, kT = 1,
     dt = 0.04: eta = 0.89-0.90 in the paper's pipe) through pipe flow,
