@@ -395,7 +395,8 @@ int dpd_profile_steps(dpd_box box, int64_t nsteps, double* ms_out);
  *   pos_out_n3, vel_out_n3:  device, n x 3 floats: x^{step0+nsteps} and
  *                            v^{step0+nsteps-1/2}; may not overlap the inputs
  *   stats:                   host, may be NULL
- * One species, no frozen particles, the default tile.  The steps are
+ * One species, no frozen particles (walls set in params act on the fluid by
+ * bounce-back alone), the default tile.  The steps are
  * launched directly on hip_stream (no graph), and the call synchronises it.
  * It calls no hipMalloc, hipFree or other allocating routine.  Errors:
  * DPD_EINVAL (geometry, params, null arrays, positions), DPD_ENOMEM when the

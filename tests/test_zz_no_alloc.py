@@ -61,6 +61,21 @@ def test_static_run_equals_workspace_run_twice_in_a_row():
     _same(_static_run(cells, pos, vel, p, seed, step0, steps), first)
 
 
+def test_static_run_with_walls_equals_workspace_run():
+    # a pipe's fluid without its frozen layer: the walls' bounce-back runs in
+    # the force kernel's write-out on both paths
+    from paper_1911_04712_amd import walls
+    cells, R, seed = (6, 11, 12), 4.0, 13
+    pos, vel, frozen = walls.carve(cells, 3.0, dpd.make_params(dt=0.01), dpd.WALL_PIPE, R, seed=seed,
+                                   equil_steps=50)
+    pos, vel = pos[~frozen], vel[~frozen]
+    p = dpd.make_params(wall_kind=dpd.WALL_PIPE, wall_h=R, flags=dpd.FLAG_BODY_UNIFORM, body_f=0.2, dt=0.01,
+                        profile_bins=6)
+    print(f"run_static walls case cells={cells} n={len(pos)}", flush=True)
+    got = _static_run(cells, pos, vel, p, seed, 0, 12)
+    _same(got, _workspace_run(cells, pos, vel, p, seed, 0, 12))
+
+
 def test_static_run_of_zero_steps_returns_the_grid_rounded_state():
     cells = (5, 6, 7)
     pos, vel = inputs.uniform_state(cells, density=3.0, seed=3)
